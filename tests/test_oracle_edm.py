@@ -1,0 +1,228 @@
+"""Pins for the oracle's FP64 distance map, gradient and Gram bound (CPU).
+
+Both oracle implementations (numpy rows in ``oracle.edm`` and the C loops in
+``oracle/c``) are held to the same pins: scipy's pdist (a library routine
+computing the same Euclidean distances, Sec. IV, Eq. (17)), integer points
+whose distances are exact integers, the d = 1 special case, central finite
+differences and torch autograd for the gradient, and the invariances any
+distance-based loss has.
+"""
+import numpy as np
+import pytest
+from scipy.spatial.distance import pdist, squareform
+
+from oracle import edm, native
+from paper_1308_1419_amd import synth
+
+
+def _packed_from_square(S):
+    N = S.shape[0]
+    return np.concatenate([S[i, : i + 1] for i in range(N)])
+
+
+IMPLS = {
+    "numpy": edm.edm64_packed,
+    "c": native.edm_packed,
+}
+
+GRADS = {
+    "numpy": edm.edm_backward64,
+    "c": native.edm_backward,
+}
+
+
+@pytest.mark.parametrize("impl", sorted(IMPLS))
+@pytest.mark.parametrize("N,d", [(1, 3), (2, 1), (37, 3), (130, 4), (64, 64)])
+def test_edm_matches_scipy_pdist(impl, N, d):
+    X = synth.uniform_points(N, d, seed=11 + N + d)
+    ref = _packed_from_square(squareform(pdist(X.astype(np.float64))))
+    got = IMPLS[impl](X)
+    assert got.shape == ref.shape
+    np.testing.assert_allclose(got, ref, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("impl", sorted(IMPLS))
+def test_edm_integer_points_exact(impl):
+    # integer vectors whose differences are Pythagorean triples/quadruples:
+    # (3,4,0) -> 5, (1,2,2) -> 3, (2,3,6) -> 7, (1,4,8) -> 9, (2,10,11) -> 15
+    base = np.array([10.0, 20.0, 30.0], dtype=np.float32)
+    offsets = [(0, 0, 0), (3, 4, 0), (1, 2, 2), (2, 3, 6), (1, 4, 8), (2, 10, 11)]
+    X = np.array([[0, 0, 0]] + [list(o) for o in offsets[1:]], dtype=np.float32) + base
+    got = IMPLS[impl](X)
+    for r, (expect) in enumerate([5.0, 3.0, 7.0, 9.0, 15.0], start=1):
+        assert got[edm.tri(r) + 0] == expect
+    # the diagonal is exactly zero
+    for i in range(X.shape[0]):
+        assert got[edm.tri(i) + i] == 0.0
+
+
+@pytest.mark.parametrize("impl", sorted(IMPLS))
+def test_edm_one_feature_is_absolute_difference(impl):
+    X = synth.uniform_points(200, 1, seed=5)
+    got = IMPLS[impl](X)
+    x = X[:, 0].astype(np.float64)
+    for i in [0, 1, 17, 199]:
+        np.testing.assert_array_equal(got[edm.tri(i): edm.tri(i) + i + 1],
+                                      np.abs(x[i] - x[: i + 1]))
+
+
+def test_edm_rows_and_full_agree_with_packed():
+    X = synth.uniform_points(150, 3, seed=9)
+    P = edm.edm64_packed(X)
+    F = edm.edm64_full(X)
+    rows = [0, 3, 77, 149]
+    for i, r64, rc in zip(rows, edm.edm64_rows(X, rows), native.edm_rows(X, rows)):
+        seg = P[edm.tri(i): edm.tri(i) + i + 1]
+        np.testing.assert_array_equal(r64, seg)
+        np.testing.assert_array_equal(rc, seg)
+        np.testing.assert_array_equal(F[i, : i + 1], seg)
+        assert np.all(np.isnan(F[i, i + 1:]))
+
+
+def test_edm_translation_invariant_and_batched():
+    data = synth.batched_sets(5, 3, 40, 3, seed=21)
+    X, off = data["X"], data["point_off"]
+    cat = edm.edm64_batched(X, off)
+    assert cat.shape[0] == int(data["out_off"][-1])
+    for s in range(5):
+        seg = cat[data["out_off"][s]: data["out_off"][s + 1]]
+        pts = X[off[s]: off[s + 1]]
+        ref = _packed_from_square(squareform(pdist(pts.astype(np.float64))))
+        np.testing.assert_allclose(seg, ref, rtol=1e-15)
+    # translating every point by an exactly representable shift changes nothing
+    shifted = (X[off[0]: off[1]].astype(np.float64) + 2.0).astype(np.float32)
+    np.testing.assert_allclose(edm.edm64_packed(shifted),
+                               edm.edm64_packed(X[off[0]: off[1]]), rtol=1e-6)
+
+
+# --------------------------------------------------------------------------
+# gradient
+# --------------------------------------------------------------------------
+
+def _stress_value(delta):
+    def f(X64):
+        D = np.concatenate([np.sqrt(((X64[i] - X64[: i + 1]) ** 2).sum(1))
+                            for i in range(X64.shape[0])])
+        N = X64.shape[0]
+        mask = np.ones_like(D, dtype=bool)
+        mask[[edm.tri(i) + i for i in range(N)]] = False
+        r = np.where(mask, D - delta, 0.0)
+        return float((r * r).sum())
+    return f
+
+
+@pytest.mark.parametrize("impl", sorted(GRADS))
+def test_stress_gradient_matches_finite_differences(impl):
+    # the small stress case: n = 64, d = 3, X ~ U[0,1), X' = X + N(0, 0.05^2)
+    X, Xp = synth.stress_inputs(64, 3, seed=synth.workload_seed(4))
+    delta = edm.edm64_packed(Xp)
+    L, D, dD = edm.stress64(X, delta)
+    if impl == "numpy":
+        g = edm.edm_backward64(X, dD)
+    else:
+        # the C oracle takes the cell gradient as FP32, so feed it a
+        # FP32-exact one: scale the FP64 residual onto the FP32 grid
+        dD32 = dD.astype(np.float32)
+        g = native.edm_backward(X, dD32)
+        g_ref = edm.edm_backward64(X, dD32.astype(np.float64))
+        np.testing.assert_allclose(g, g_ref, rtol=1e-12, atol=1e-14)
+        g = edm.edm_backward64(X, dD)
+    fd = edm.central_differences(_stress_value(delta), X, h=1e-6)
+    assert np.max(np.abs(g - fd)) <= 1e-7 * max(1.0, np.max(np.abs(g)))
+    assert L > 0
+
+
+def test_gradient_matches_torch_autograd():
+    torch = pytest.importorskip("torch")
+    X = synth.uniform_points(90, 4, seed=3)
+    rng = np.random.default_rng(4)
+    dD = rng.standard_normal(edm.tri(90))
+    Xt = torch.tensor(X.astype(np.float64), requires_grad=True)
+    N = X.shape[0]
+    ii, jj = np.tril_indices(N, k=-1)
+    diff = Xt[torch.as_tensor(ii)] - Xt[torch.as_tensor(jj)]
+    D = torch.sqrt((diff * diff).sum(1))
+    w = torch.as_tensor(dD[ii * (ii + 1) // 2 + jj])
+    (D * w).sum().backward()
+    np.testing.assert_allclose(edm.edm_backward64(X, dD), Xt.grad.numpy(),
+                               rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("impl", sorted(GRADS))
+def test_gradient_invariances(impl):
+    X = synth.uniform_points(120, 3, seed=8)
+    rng = np.random.default_rng(1)
+    dD = rng.standard_normal(edm.tri(120)).astype(np.float32)
+    g = GRADS[impl](X, dD)
+    X64 = X.astype(np.float64)
+    scale = np.abs(g).max()
+    # translation invariance of any function of distances: sum_i dX_i = 0
+    assert np.all(np.abs(g.sum(0)) <= 1e-11 * scale * 120)
+    # rotation invariance (d = 3): sum_i x_i x dX_i = 0
+    torque = np.cross(X64, g).sum(0)
+    assert np.all(np.abs(torque) <= 1e-11 * scale * 120)
+
+
+def test_stress_zero_at_target():
+    X = synth.uniform_points(50, 3, seed=2)
+    L, dX = edm.stress_grad64(X, edm.edm64_packed(X))
+    assert L == 0.0
+    assert np.all(dX == 0.0)
+
+
+def test_gradient_ignores_diagonal_and_coincident_points():
+    X = synth.uniform_points(10, 3, seed=6)
+    X[7] = X[2]  # a coincident pair: D = 0, its term is taken as 0
+    dD = np.zeros(edm.tri(10))
+    for i in range(10):
+        dD[edm.tri(i) + i] = 1e3  # diagonal cells carry no gradient
+    dD[edm.tri(7) + 2] = 5.0
+    assert np.all(edm.edm_backward64(X, dD) == 0.0)
+    assert np.all(native.edm_backward(X, dD.astype(np.float32)) == 0.0)
+
+
+# --------------------------------------------------------------------------
+# BF16 Gram bound
+# --------------------------------------------------------------------------
+
+def _round_bf16(x32):
+    """Round-to-nearest-even FP32 -> BF16, returned as FP32 values."""
+    b = np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (b >> 16) & 1
+    r = ((b + 0x7FFF + lsb) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def test_bf16_rounding_helper():
+    vals = np.array([1.0, 1.00390625, 1.005859375, -3.0, 0.0], dtype=np.float32)
+    # 1 + 2^-8 is the midpoint between 1 and 1 + 2^-7: ties to even -> 1
+    r = _round_bf16(vals)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == np.float32(1.0078125)
+    assert r[3] == -3.0 and r[4] == 0.0
+
+
+def test_gram_bound_covers_simulated_bf16_fp32_gram():
+    # simulate the Gram form step by step in FP32 on BF16-rounded inputs
+    # (sequential FP32 sums, a worse order than a tree) and check that the
+    # stated bound holds for every pair that would not be recomputed
+    X, pairs = synth.gaussian_with_near_duplicates(600, 64, seed=33)
+    Xb = _round_bf16(X)
+    n = np.zeros(600, dtype=np.float32)
+    for k in range(64):
+        n = n + Xb[:, k] * Xb[:, k]
+    dot = np.zeros((600, 600), dtype=np.float32)
+    for k in range(64):
+        dot = dot + np.outer(Xb[:, k], Xb[:, k]).astype(np.float32)
+    G = (n[:, None] + n[None, :]) - np.float32(2.0) * dot
+    Dg = np.sqrt(np.maximum(G, 0)).astype(np.float64)
+    D = squareform(pdist(X.astype(np.float64)))
+    norms = np.linalg.norm(X.astype(np.float64), axis=1)
+    bound = edm.gram_bound(norms[:, None], norms[None, :], D, 64)
+    recompute = G <= 0.25 * (n[:, None] + n[None, :])
+    ok = np.abs(Dg - D) <= bound
+    assert np.all(ok | recompute)
+    # every planted near-duplicate and the diagonal fall under the threshold
+    assert np.all(recompute[pairs[:, 0], pairs[:, 1]])
+    assert np.all(np.diag(recompute))
+    # and the bound is not vacuous: well below the typical distance
+    assert np.median(bound[~recompute]) < 0.02 * np.median(D[~recompute])
