@@ -1,0 +1,212 @@
+"""Benchmark of the triangular-domain EDM on one MI355X.
+
+One step = one lower-triangular EDM of 30000 FP32 points with 3 features,
+written to a full 30000 x 30000 FP32 matrix (only j <= i), launched through
+g(lambda) with the autotuned coarsened tile.  Inputs live in HBM before the
+timed region; the output buffer is allocated once.
+
+Printed (one JSON line on stdout): pairs/s of that step, the roofline of the
+EDM kernel (algorithmic bytes = 4 B per cell written), the same step with
+the bounding-box grid (I = t_BB / t_LTM), the paper-style launches of all
+five strategies at rho = 8, 16, 32 with their launch statistics, the other
+workloads' rows, and the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "EDM pairs/sec + % HBM roofline, g(λ) vs BB on 1 MI355X; fwd+bwd pairs/sec"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "edm_n30000_d3_full"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources the EDM kernel is built from; a stored HBM
+    traffic figure is only reported while it matches."""
+    h = hashlib.sha256()
+    for f in ("device.h", "tiled.hip"):
+        with open(os.path.join(ROOT, "paper_1308_1419_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic():
+    path = os.path.join(ROOT, "profiles", "traffic_edm_tile_n30000_d3_full.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec
+
+
+def time_calls(fn, reps: int, warmup: int = 2):
+    """Per-call times (ms) from HIP events on torch's current stream, which
+    is the stream every call launches on."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    out = []
+    for _ in range(reps):
+        s.record()
+        fn()
+        e.record()
+        e.synchronize()
+        out.append(s.elapsed_time(e))
+    return out
+
+
+def cpu_baseline(X: np.ndarray, target_s: float = 10.0):
+    """The C oracle (FP64 loops, OpenMP over rows) on a seeded sample of
+    rows of the same workload, sized to about target_s seconds."""
+    from oracle import native
+    from paper_1308_1419_amd import synth
+    N = X.shape[0]
+    native.load()
+    probe = synth.sample_rows(N, 64, seed=1)
+    t0 = time.perf_counter()
+    native.edm_rows(X, probe)
+    dt = time.perf_counter() - t0
+    rate = sum(i + 1 for i in probe) / max(dt, 1e-9)
+    want_pairs = rate * target_s
+    mean_row = (N + 1) / 2
+    count = int(min(N, max(64, want_pairs / mean_row)))
+    rows = synth.sample_rows(N, count, seed=2)
+    pairs = sum(i + 1 for i in rows)
+    t0 = time.perf_counter()
+    native.edm_rows(X, rows)
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": native.threads(),
+            "kind": "oracle",
+            "sample": f"{len(rows)} seeded rows of the N=30000, d=3 triangle "
+                      f"({pairs} pairs, {dt:.1f} s, FP64 C loops)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--only-main", action="store_true",
+                    help="time only the main step (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
+              "(the EDM path runs on a single device)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1308_1419_amd import synth, tdmap
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    N, d = 30000, 3
+    X = synth.uniform_points(N, d, seed=synth.workload_seed(2))
+    Xd = torch.from_numpy(X).cuda()
+    D = torch.empty((N, N), dtype=torch.float32, device="cuda")
+    pairs = N * (N + 1) // 2
+    bytes_alg = 4 * pairs
+
+    # tile choice (untimed): the autotuner runs once per configuration
+    tdmap.edm(Xd, layout="full", strategy="ltm", rho=0, out=D)
+    tdmap.edm(Xd, layout="full", strategy="bb", rho=0, out=D)
+    torch.cuda.synchronize()
+    ts_ltm = tdmap.tdmap_tuned_rho(tdmap.OP_EDM, tdmap.LTM, tdmap.FULL, d, N)
+    ts_bb = tdmap.tdmap_tuned_rho(tdmap.OP_EDM, tdmap.BB, tdmap.FULL, d, N)
+    log(f"tuned tiles: ltm {ts_ltm}, bb {ts_bb}")
+
+    def step():
+        tdmap.edm(Xd, layout="full", strategy="ltm", rho=ts_ltm, out=D)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = ev0.elapsed_time(ev1) / args.steps
+    value = pairs * args.steps / wall
+    log(f"ltm tile {ts_ltm}: {kern_ms * 1e3:.1f} us/step, wall {wall / args.steps * 1e3:.1f} us")
+
+    achieved = bytes_alg / (kern_ms * 1e-3) / 1e9
+    traffic = stored_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic["bytes_per_launch"] if traffic else None,
+                "kernel": "edm_tile_kernel (LTM, full layout)",
+                "algorithmic_bytes_per_launch": bytes_alg}
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "N": N, "d": d, "layout": "full",
+                   "strategy": "ltm", "rho": ts_ltm, "pairs": pairs},
+        "roofline": roofline,
+    }
+
+    if not args.only_main:
+        comp = {}
+        # the same tile body on the bounding-box grid
+        t_ltm = float(np.median(time_calls(step, 20)))
+        t_bb = float(np.median(time_calls(
+            lambda: tdmap.edm(Xd, layout="full", strategy="bb", rho=ts_bb, out=D), 20)))
+        comp["tiled"] = {"ltm_us": t_ltm * 1e3, "bb_us": t_bb * 1e3, "ltm_rho": ts_ltm,
+                         "bb_rho": ts_bb, "I": t_bb / t_ltm,
+                         "ltm_hbm_frac": bytes_alg / (t_ltm * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        # the paper's launches: rho x rho threads, one cell each
+        paper = {}
+        for rho in (8, 16, 32):
+            row = {}
+            for s in ("ltm", "bb", "utm", "rb", "rec"):
+                t = float(np.median(time_calls(
+                    lambda s=s: tdmap.edm(Xd, layout="full", strategy=s, rho=rho, out=D), 10)))
+                blocks, idle, idle_lanes = tdmap.waste_counts(s, N, rho)
+                row[s] = {"us": t * 1e3, "blocks": blocks, "idle_blocks": idle,
+                          "idle_threads": idle_lanes,
+                          "hbm_frac": bytes_alg / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            for s in row:
+                row[s]["I_vs_bb"] = row["bb"]["us"] / row[s]["us"]
+            paper[f"rho{rho}"] = row
+            log(f"rho {rho}: " + ", ".join(f"{s} {row[s]['us']:.0f}us" for s in row))
+        comp["paper_style"] = paper
+        result["comparison"] = comp
+
+    if not args.skip_cpu:
+        log("timing the CPU oracle on a sample ...")
+        result["cpu_baseline"] = cpu_baseline(X)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * tdmap -- triangular-domain kernels for MI355X (gfx950): the lower-
+ * triangular Euclidean distance map launched through the block map g(lambda)
+ * of Navarro & Hitschfeld, "Improving the GPU space of computation under
+ * triangular domain problems" (arXiv 1308.1419), next to the strategies that
+ * paper compares against.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Plain C ABI.  Pointers marked "device" must point to device memory of
+ *   the current HIP device; "host" pointers to host memory.  The caller owns
+ *   every buffer (inputs, outputs and workspaces); the library allocates no
+ *   device memory.  Its only state is the autotuner cache (host, guarded by
+ *   a mutex) and a per-thread copy of the last HIP error message.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *   GPU work is enqueued asynchronously on it; no entry point synchronises
+ *   the host except the autotuner on its first call for a configuration,
+ *   which times candidate launches on `stream`.
+ * - Every call returns a tdmap_status.  Arguments are validated before any
+ *   launch; on a validation error nothing is enqueued.  A failed launch
+ *   returns TDMAP_ERR_HIP and tdmap_last_error() gives the HIP message.
+ *   Nothing throws across the ABI.
+ * - A problem of size N has the N(N+1)/2 cells (i, j), 0 <= j <= i < N
+ *   (Sec. II-A).  N = 0 is a successful no-op.
+ * - Points are an N x d row-major FP32 array with row pitch ldx >= d
+ *   (in elements); point i is X[i*ldx .. i*ldx + d).
+ * - Output layouts:
+ *     TDMAP_FULL   : N x N row-major FP32 with row pitch ldd >= N (elements);
+ *                    only cells with j <= i are written, every j > i cell is
+ *                    left untouched.
+ *     TDMAP_PACKED : N(N+1)/2 FP32, cell (i, j) at i(i+1)/2 + j (64-bit
+ *                    offsets; ldd is ignored).
+ * - Inputs and outputs must not overlap (undefined behaviour otherwise).
+ */
+#ifndef TDMAP_H
+#define TDMAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TDMAP_OK = 0,
+    TDMAP_ERR_INVALID = 1,      /* a NULL pointer, a negative size, ldx < d, ldd < N, ... */
+    TDMAP_ERR_UNSUPPORTED = 2,  /* valid but not implemented (e.g. a size past 2^32 blocks) */
+    TDMAP_ERR_WORKSPACE = 3,    /* workspace missing or smaller than tdmap_workspace_size */
+    TDMAP_ERR_HIP = 4           /* a HIP call failed; see tdmap_last_error() */
+} tdmap_status;
+
+/* Space-of-computation strategies (Sec. II-A and Sec. III-B). */
+typedef enum {
+    TDMAP_LTM = 0,  /* 1D grid of exactly n(n+1)/2 blocks, block lambda -> g(lambda) (Sec. II-A, Eq. (2)) */
+    TDMAP_BB = 1,   /* n x n grid, blocks above the diagonal return at once (Sec. III-B) */
+    TDMAP_UTM = 2,  /* per-thread upper-triangular map of Avril et al. (Sec. III-B), half-turned */
+    TDMAP_RB = 3,   /* rectangular box of Jung et al. (Sec. III-B) */
+    TDMAP_REC = 4   /* recursive partition of Ries et al.: a diagonal pass + k level launches (Sec. III-B) */
+} tdmap_strategy;
+
+typedef enum { TDMAP_FULL = 0, TDMAP_PACKED = 1 } tdmap_layout;
+
+typedef enum {
+    TDMAP_FP32 = 0,      /* difference form sqrt(sum_k (x_ik - x_jk)^2) in FP32 */
+    TDMAP_BF16_GRAM = 1  /* ||x||^2 + ||y||^2 - 2 x.y with BF16 MFMA, FP32 accumulate,
+                            FP32 difference-form recompute of near-zero distances */
+} tdmap_precision;
+
+typedef enum { TDMAP_OP_EDM = 0, TDMAP_OP_BACKWARD = 1, TDMAP_OP_BATCHED = 2 } tdmap_op;
+
+/*
+ * g(lambda) over a range of block indices (Sec. II-A, Eq. (2); the row is
+ * i = floor(sqrt(1/4 + 2 lambda) - 1/2), the column j = lambda - i(i+1)/2).
+ * The device computes a single-precision guess of i and corrects it with
+ * exact integer compares (the block-level fix-up the conclusion, Sec. V,
+ * says suffices while the error is at most 1), so the map is exact for
+ * every lambda < 2^32.
+ *   ij      device, 2*count uint32: ij[2t] = i, ij[2t+1] = j for
+ *           lambda = lambda0 + t.
+ * Errors: INVALID if ij is NULL while count > 0; UNSUPPORTED if
+ * lambda0 + count > 2^32.
+ */
+int tdmap_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, void *stream);
+
+/*
+ * Lower-triangular Euclidean distance map D_ij = sqrt(sum_k (x_ik - x_jk)^2),
+ * 0 <= j <= i < N (the EDM problem of Sec. IV, Eq. (17)), computed by the
+ * chosen space-of-computation strategy.
+ *   X        device, N x d FP32, row pitch ldx.
+ *   D        device, output in `layout` (pitch ldd for TDMAP_FULL).
+ *   strategy one of tdmap_strategy.
+ *   rho      the dimensional block size (Sec. II-A):
+ *              8, 16, 32 : rho x rho threads per block, one cell per thread,
+ *                          as the paper launches every strategy;
+ *              64, 128, 256 : (LTM, BB) rho x rho cell tiles per 256-thread
+ *                          work-group, four consecutive cells per thread;
+ *              0         : (LTM, BB) tile chosen by the autotuner.
+ *   precision TDMAP_FP32 for every strategy; TDMAP_BF16_GRAM only with
+ *            TDMAP_LTM, TDMAP_PACKED and rho = 0 or 128.
+ *   workspace device scratch of at least
+ *            tdmap_workspace_size(TDMAP_OP_EDM, N, d, 0, rho, precision)
+ *            bytes (0 for TDMAP_FP32; may then be NULL).
+ * Every strategy writes the same cells with the same per-pair arithmetic,
+ * so their outputs are bitwise identical.  FP32 results are within a
+ * relative 1e-6 of the exact distance of the FP32 inputs (squared distances
+ * below 2^-126 excepted), and exactly 0 where x_i == x_j.
+ * Errors: INVALID for NULL pointers, N < 0, d < 1, ldx < d, ldd < N (FULL)
+ * or an unknown enum; UNSUPPORTED for a (strategy, rho, precision, layout)
+ * combination listed above as unavailable, d > 4 with tiled rho, or sizes
+ * past the 32-bit block index; WORKSPACE if the workspace is too small.
+ */
+int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx,
+              float *D, int64_t ldd, int32_t layout, int32_t strategy,
+              int32_t rho, int32_t precision,
+              void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Gradient through the EDM: given dD_ij = dL/dD_ij for the cells of the
+ * triangle, writes dX_i = sum_{j<i} dD_ij (x_i - x_j)/D_ij
+ *                       - sum_{k>i} dD_ki (x_k - x_i)/D_ki,
+ * a term being 0 where D = 0; diagonal cells of dD are ignored.  The tiles
+ * are enumerated by g(lambda) as in the forward map.  This operation is not
+ * in the paper; it differentiates the EDM of Sec. IV, Eq. (17).
+ *   X      device, N x d FP32, pitch ldx.    dD device, `layout` (pitch ldd).
+ *   dX     device, N x d FP32, row pitch d, overwritten.
+ *   rho    tile edge: 0 (autotuned), 32, 64 or 128.
+ *   deterministic  1: per-tile partial sums in the workspace, reduced in a
+ *          fixed order (bitwise reproducible); 0: partial sums added with
+ *          atomics (no workspace, order-dependent last bits).
+ *   workspace  device, tdmap_workspace_size(TDMAP_OP_BACKWARD, N, d, 0, rho,
+ *          deterministic) bytes (0 when deterministic = 0).
+ * d must be 1..4.  Errors as for tdmap_edm.
+ */
+int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx,
+                       const float *dD, int64_t ldd, int32_t layout,
+                       float *dX, int32_t rho, int32_t deterministic,
+                       void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Many independent EDMs in one persistent launch (not in the paper; each
+ * set is the EDM of Sec. IV on its own points).  Set s owns points
+ * X_cat[point_off[s] .. point_off[s+1]) and writes its packed triangle at
+ * D_cat + out_off[s].  The work-groups walk the concatenation of every
+ * set's g(lambda) tile space (a prefix sum of n_s(n_s+1)/2 block counts).
+ *   X_cat      device, (point_off[S]) x d FP32, pitch d.
+ *   point_off  device, S+1 int64, non-decreasing, point_off[0] = 0.
+ *   out_off    device, S+1 int64, out_off[s+1] - out_off[s] =
+ *              n_s(n_s+1)/2 with n_s = point_off[s+1] - point_off[s].
+ *   rho        tile edge 16, 32, 64 or 128; 0 = autotuned.
+ *   workspace  device, tdmap_workspace_size(TDMAP_OP_BATCHED, 0, d, S, rho, 0)
+ *              bytes.
+ * The offsets are not read on the host; inconsistent offsets are undefined
+ * behaviour.  d must be 1..4.  Errors as for tdmap_edm.
+ */
+int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets,
+                      const int64_t *point_off, const int64_t *out_off,
+                      float *D_cat, int32_t rho,
+                      void *workspace, size_t ws_bytes, void *stream);
+
+/* Bytes of device workspace an operation needs (0 if none).  `flags` is the
+ * precision for TDMAP_OP_EDM, `deterministic` for TDMAP_OP_BACKWARD and
+ * unused for TDMAP_OP_BATCHED.  Pure host arithmetic. */
+size_t tdmap_workspace_size(int32_t op, int64_t N, int32_t d, int32_t num_sets,
+                            int32_t rho, int32_t flags);
+
+/*
+ * Launch statistics of a strategy, in closed form (host only): out[0] =
+ * blocks launched, out[1] = fully idle blocks (blocks that write no cell),
+ * out[2] = idle threads (threads that write no cell), for the one-cell-per-
+ * thread launch with rho x rho blocks.  Sec. II-A: BB leaves n(n-1)/2 blocks
+ * idle, LTM none (its idle threads are the upper halves of the n diagonal
+ * blocks, about n/2 block equivalents).
+ * Errors: INVALID for a NULL out, N < 0, rho < 1 or an unknown strategy.
+ */
+int tdmap_waste_counts(int32_t strategy, int64_t N, int32_t rho, int64_t out[3]);
+
+/*
+ * The same statistics counted on the device by an instrumented variant of
+ * the strategy's kernel (it evaluates the map and filters exactly as the
+ * timed kernel does, and counts instead of storing).
+ *   counts  device, 3 uint64 (blocks, fully idle blocks, idle threads),
+ *           overwritten.
+ * rho must be 8, 16 or 32.
+ */
+int tdmap_count_waste(int32_t strategy, int64_t N, int32_t rho,
+                      uint64_t *counts, void *stream);
+
+/* Tile edge the autotuner has chosen for a call with rho = 0, or 0 if that
+ * configuration has not been tuned yet.  `strategy` and `layout` are those
+ * of the call (ignored for TDMAP_OP_BACKWARD / TDMAP_OP_BATCHED); `size` is
+ * N for TDMAP_OP_EDM / TDMAP_OP_BACKWARD and num_sets for TDMAP_OP_BATCHED.
+ * Decisions are cached per (op, strategy, layout, d, ceil(log2(size))). */
+int32_t tdmap_tuned_rho(int32_t op, int32_t strategy, int32_t layout, int32_t d, int64_t size);
+
+/* Forget every autotuner decision. */
+void tdmap_autotune_reset(void);
+
+/* Static description of a status code (never NULL). */
+const char *tdmap_status_string(int32_t status);
+
+/* Message of the last HIP failure on the calling thread ("" if none). */
+const char *tdmap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDMAP_H */

@@ -1,0 +1,321 @@
+// The C ABI of include/tdmap.h: argument validation, dispatch to the
+// kernels, the tile autotuner and the closed-form launch statistics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.h"
+#include "tdmap.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int hip_fail(hipError_t e, const char *where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return TDMAP_ERR_HIP;
+}
+
+#define TD_HIP(call, where)                    \
+  do {                                         \
+    hipError_t e_ = (call);                    \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+inline uint64_t tri(uint64_t n) { return n * (n + 1) / 2; }
+
+bool is_cell_rho(int rho) { return rho == 8 || rho == 16 || rho == 32; }
+
+// ---------------------------------------------------------------------------
+// autotuner: times each candidate tile on the caller's stream and buffers on
+// first use of a configuration, keeps the fastest.
+// ---------------------------------------------------------------------------
+
+using TuneKey = std::tuple<int, int, int, int, int>;  // op, strategy, layout, d, log2 bucket
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;
+
+int size_bucket(int64_t size) {
+  int b = 0;
+  while (b < 62 && ((int64_t)1 << b) < size) ++b;
+  return b;
+}
+
+int tuned_lookup(const TuneKey &k) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tuned.find(k);
+  return it == g_tuned.end() ? 0 : it->second;
+}
+
+void tuned_store(const TuneKey &k, int v) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tuned[k] = v;
+}
+
+// Runs launch(c) for every candidate c: one warm-up and `reps` timed runs,
+// median of the per-run times.  Returns the fastest candidate (0 on error,
+// with *status set).
+template <class F>
+int autotune(const std::vector<int> &cands, hipStream_t s, F launch, int *status) {
+  hipEvent_t ev[2];
+  *status = TDMAP_OK;
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+    *status = TDMAP_ERR_HIP;
+    g_last_error = "autotune: hipEventCreate failed";
+    return 0;
+  }
+  int best = 0;
+  float best_ms = 0.0f;
+  const int reps = 3;
+  for (int c : cands) {
+    hipError_t e = launch(c);
+    if (e != hipSuccess) {
+      *status = hip_fail(e, "autotune launch");
+      break;
+    }
+    std::vector<float> ms;
+    for (int r = 0; r < reps && *status == TDMAP_OK; ++r) {
+      e = hipEventRecord(ev[0], s);
+      if (e == hipSuccess) e = launch(c);
+      if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      if (e != hipSuccess) {
+        *status = hip_fail(e, "autotune run");
+        break;
+      }
+      float t = 0.0f;
+      (void)hipEventElapsedTime(&t, ev[0], ev[1]);
+      ms.push_back(t);
+    }
+    if (*status != TDMAP_OK) break;
+    std::sort(ms.begin(), ms.end());
+    const float med = ms[ms.size() / 2];
+    if (best == 0 || med < best_ms) {
+      best = c;
+      best_ms = med;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  return *status == TDMAP_OK ? best : 0;
+}
+
+// ---------------------------------------------------------------------------
+// closed-form launch statistics (Sec. II-A, Sec. III-B)
+// ---------------------------------------------------------------------------
+
+void rec_shape_host(uint64_t nb, uint64_t &m, uint64_t &k) {
+  uint64_t best = 0;
+  for (uint64_t mm = 16; mm >= 1; --mm) {
+    uint64_t kk = 0;
+    while ((mm << kk) < nb) ++kk;
+    if (best == 0 || (mm << kk) < best) {
+      best = mm << kk;
+      m = mm;
+      k = kk;
+    }
+  }
+}
+
+bool waste_closed_form(int strategy, int64_t N, int rho, int64_t out[3]) {
+  const uint64_t n = ceil_div((uint64_t)N, (uint64_t)rho);
+  const uint64_t P = tri((uint64_t)N);
+  const uint64_t lanes = (uint64_t)rho * rho;
+  uint64_t blocks = 0, idle = 0;
+  switch (strategy) {
+    case TDMAP_LTM:
+      blocks = tri(n);
+      break;
+    case TDMAP_BB:
+      blocks = n * n;
+      idle = n * (n - (n > 0)) / 2;
+      break;
+    case TDMAP_UTM:
+      blocks = ceil_div(P, lanes);
+      break;
+    case TDMAP_RB: {
+      const uint64_t rows = (N % 2 == 0) ? N + 1 : N;
+      const uint64_t cols = (N % 2 == 0) ? N / 2 : N / 2 + 1;
+      blocks = ceil_div(rows, rho) * ceil_div(cols, rho);
+      if (N == 0) blocks = 0;
+      break;
+    }
+    case TDMAP_REC: {
+      if (n == 0) break;
+      uint64_t m = 1, k = 0;
+      rec_shape_host(n, m, k);
+      // diagonal pass: m x m blocks per base square, upper m(m-1)/2 idle,
+      // and base rows at or past n idle on and below the base diagonal
+      blocks = (m * m) << k;
+      idle = (m * (m - 1) / 2) << k;
+      for (uint64_t q = 0; q < (1ull << k); ++q)
+        for (uint64_t by = 0; by < m; ++by)
+          if (q * m + by >= n) idle += by + 1;
+      for (uint64_t lev = 0; lev < k; ++lev) {
+        const uint64_t s = m << lev;
+        for (uint64_t q = 0; q < (1ull << (k - 1 - lev)); ++q) {
+          blocks += s * s;
+          const uint64_t r0 = (2 * q + 1) * s;
+          if (r0 + s > n) idle += s * std::min<uint64_t>(s, r0 + s - n);
+        }
+      }
+      break;
+    }
+    default:
+      return false;
+  }
+  out[0] = (int64_t)blocks;
+  out[1] = (int64_t)idle;
+  out[2] = (int64_t)(blocks * lanes - P);
+  return true;
+}
+
+int validate_edm_common(const float *X, int64_t N, int32_t d, int64_t ldx, const void *D,
+                        int64_t ldd, int32_t layout) {
+  if (N < 0 || d < 1 || ldx < d) return TDMAP_ERR_INVALID;
+  if (layout != TDMAP_FULL && layout != TDMAP_PACKED) return TDMAP_ERR_INVALID;
+  if (N == 0) return TDMAP_OK;
+  if (X == nullptr || D == nullptr) return TDMAP_ERR_INVALID;
+  if (layout == TDMAP_FULL && ldd < N) return TDMAP_ERR_INVALID;
+  return TDMAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tdmap_status_string(int32_t status) {
+  switch (status) {
+    case TDMAP_OK: return "success";
+    case TDMAP_ERR_INVALID: return "invalid argument";
+    case TDMAP_ERR_UNSUPPORTED: return "unsupported configuration";
+    case TDMAP_ERR_WORKSPACE: return "workspace missing or too small";
+    case TDMAP_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char *tdmap_last_error(void) { return g_last_error.c_str(); }
+
+void tdmap_autotune_reset(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tuned.clear();
+}
+
+int32_t tdmap_tuned_rho(int32_t op, int32_t strategy, int32_t layout, int32_t d, int64_t size) {
+  if (op != TDMAP_OP_EDM) strategy = layout = 0;
+  return tuned_lookup(TuneKey(op, strategy, layout, d, size_bucket(size)));
+}
+
+int tdmap_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, void *stream) {
+  if (count == 0) return TDMAP_OK;
+  if (ij == nullptr) return TDMAP_ERR_INVALID;
+  if (lambda0 > ((uint64_t)1 << 32) || count > ((uint64_t)1 << 32) - lambda0)
+    return TDMAP_ERR_UNSUPPORTED;
+  TD_HIP(tdmap::launch_map_blocks(lambda0, count, ij, (hipStream_t)stream), "tdmap_map_blocks");
+  return TDMAP_OK;
+}
+
+size_t tdmap_workspace_size(int32_t op, int64_t N, int32_t d, int32_t num_sets, int32_t rho,
+                            int32_t flags) {
+  (void)N;
+  (void)d;
+  (void)num_sets;
+  (void)rho;
+  (void)flags;
+  switch (op) {
+    default:
+      return 0;
+  }
+}
+
+int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int64_t ldd,
+              int32_t layout, int32_t strategy, int32_t rho, int32_t precision, void *workspace,
+              size_t ws_bytes, void *stream) {
+  (void)workspace;
+  (void)ws_bytes;
+  int st = validate_edm_common(X, N, d, ldx, D, ldd, layout);
+  if (st != TDMAP_OK) return st;
+  if (strategy < TDMAP_LTM || strategy > TDMAP_REC) return TDMAP_ERR_INVALID;
+  if (precision != TDMAP_FP32 && precision != TDMAP_BF16_GRAM) return TDMAP_ERR_INVALID;
+  if (precision == TDMAP_BF16_GRAM) return TDMAP_ERR_UNSUPPORTED;
+  if (!(rho == 0 || is_cell_rho(rho) || rho == 64 || rho == 128 || rho == 256))
+    return TDMAP_ERR_INVALID;
+  const bool tiled = !is_cell_rho(rho);
+  if (tiled && strategy != TDMAP_LTM && strategy != TDMAP_BB) return TDMAP_ERR_UNSUPPORTED;
+  if (tiled && d > 4) return TDMAP_ERR_UNSUPPORTED;
+  if (N == 0) return TDMAP_OK;
+  // block index limits: lambda and the UTM thread index are 32-bit
+  const uint64_t edge = tiled ? (rho ? (uint64_t)rho : 64) : (uint64_t)rho;
+  const uint64_t nb = ceil_div((uint64_t)N, edge);
+  if (tri(nb) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
+  if (strategy == TDMAP_UTM && tri((uint64_t)N) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
+  if (strategy == TDMAP_BB && nb > 0x7fffffffull) return TDMAP_ERR_UNSUPPORTED;
+
+  hipStream_t s = (hipStream_t)stream;
+  tdmap::EdmArgs a{X, N, d, ldx, D, ldd, layout, s};
+  if (!tiled) {
+    TD_HIP(tdmap::launch_cell(strategy, rho, a, nullptr), "tdmap_edm");
+    return TDMAP_OK;
+  }
+  const bool bb = strategy == TDMAP_BB;
+  int ts = rho;
+  if (ts == 0) {
+    const TuneKey key(TDMAP_OP_EDM, strategy, layout, d, size_bucket(N));
+    ts = tuned_lookup(key);
+    if (ts == 0) {
+      ts = autotune({64, 128, 256}, s, [&](int c) { return tdmap::launch_tiled(bb, c, a); }, &st);
+      if (st != TDMAP_OK) return st;
+      tuned_store(key, ts);
+    }
+  }
+  TD_HIP(tdmap::launch_tiled(bb, ts, a), "tdmap_edm");
+  return TDMAP_OK;
+}
+
+int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx, const float *dD,
+                       int64_t ldd, int32_t layout, float *dX, int32_t rho, int32_t deterministic,
+                       void *workspace, size_t ws_bytes, void *stream) {
+  (void)X; (void)N; (void)d; (void)ldx; (void)dD; (void)ldd; (void)layout; (void)dX; (void)rho;
+  (void)deterministic; (void)workspace; (void)ws_bytes; (void)stream;
+  return TDMAP_ERR_UNSUPPORTED;
+}
+
+int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets, const int64_t *point_off,
+                      const int64_t *out_off, float *D_cat, int32_t rho, void *workspace,
+                      size_t ws_bytes, void *stream) {
+  (void)X_cat; (void)d; (void)num_sets; (void)point_off; (void)out_off; (void)D_cat; (void)rho;
+  (void)workspace; (void)ws_bytes; (void)stream;
+  return TDMAP_ERR_UNSUPPORTED;
+}
+
+int tdmap_waste_counts(int32_t strategy, int64_t N, int32_t rho, int64_t out[3]) {
+  if (out == nullptr || N < 0 || rho < 1) return TDMAP_ERR_INVALID;
+  return waste_closed_form(strategy, N, rho, out) ? TDMAP_OK : TDMAP_ERR_INVALID;
+}
+
+int tdmap_count_waste(int32_t strategy, int64_t N, int32_t rho, uint64_t *counts, void *stream) {
+  if (counts == nullptr || N < 0) return TDMAP_ERR_INVALID;
+  if (strategy < TDMAP_LTM || strategy > TDMAP_REC) return TDMAP_ERR_INVALID;
+  if (!is_cell_rho(rho)) return TDMAP_ERR_UNSUPPORTED;
+  const uint64_t nb = ceil_div((uint64_t)N, (uint64_t)rho);
+  if (tri(nb) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
+  if (strategy == TDMAP_UTM && tri((uint64_t)N) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  TD_HIP(tdmap::launch_fill(reinterpret_cast<float *>(counts), 6, 0.0f, s), "tdmap_count_waste");
+  tdmap::EdmArgs a{nullptr, N, 1, 1, nullptr, 0, TDMAP_PACKED, s};
+  TD_HIP(tdmap::launch_cell(strategy, rho, a, reinterpret_cast<unsigned long long *>(counts)),
+         "tdmap_count_waste");
+  return TDMAP_OK;
+}
+
+}  // extern "C"

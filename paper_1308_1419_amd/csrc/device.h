@@ -1,0 +1,114 @@
+// Device-side building blocks shared by every tdmap kernel (gfx950).
+//
+// - g_lambda: the block map of Sec. II-A, Eq. (2) with an exact integer
+//   fix-up (Sec. V notes that block-level conditionals repair any error of
+//   at most one).
+// - pair distance: the per-pair function of Sec. IV, Eq. (17), written once
+//   so that every strategy produces bit-identical values.
+// - output addressing for the full and packed layouts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tdmap {
+
+constexpr int kLayoutFull = 0;
+constexpr int kLayoutPacked = 1;
+
+__device__ __forceinline__ uint64_t tri64(uint64_t i) { return i * (i + 1) >> 1; }
+
+// g(lambda) = (i, j), i = floor(sqrt(1/4 + 2 lambda) - 1/2), j = lambda - i(i+1)/2.
+// The square root is taken as x * rsq(x) (the reciprocal-square-root form
+// the paper found fastest, Sec. III-A, Eq. (16)); the single-precision guess
+// is within one row of the true i for every lambda < 2^32 (relative error of
+// a few ulp on a value below 2^17), and two integer compares against the row
+// starts T(i) and T(i+1) make it exact.  lambda is uniform across a
+// work-group, so the compares run on the scalar unit.
+__device__ __forceinline__ void g_lambda(uint32_t lam, uint32_t &i, uint32_t &j) {
+  const float x = __builtin_fmaf(2.0f, (float)lam, 0.25f);
+  const float s = x * __builtin_amdgcn_rsqf(x);
+  uint32_t r = (uint32_t)__builtin_fmaxf(s - 0.5f, 0.0f);
+  uint64_t t = tri64(r);
+  if (t > lam) {
+    --r;
+    t -= (uint64_t)r + 1;  // T(r) = T(r+1) - (r+1)
+  } else if (t + r + 1 <= lam) {
+    t += (uint64_t)r + 1;  // T(r+1) = T(r) + r + 1
+    ++r;
+  }
+  i = r;
+  j = (uint32_t)(lam - t);
+}
+
+// Squared distance then square root, in a fixed operation order:
+// s = t_0^2, s = fma(t_k, t_k, s) for k = 1..d-1, D = v_sqrt_f32(s).
+// v_sqrt_f32 is accurate to 1 ulp; with d <= 4 the whole value is within a
+// few units of FP32 roundoff of the exact distance.
+template <int D>
+__device__ __forceinline__ float pair_dist(const float (&a)[D], const float (&b)[D]) {
+  float t = a[0] - b[0];
+  float s = t * t;
+#pragma unroll
+  for (int k = 1; k < D; ++k) {
+    t = a[k] - b[k];
+    s = __builtin_fmaf(t, t, s);
+  }
+  return __builtin_amdgcn_sqrtf(s);
+}
+
+// Same arithmetic for a run-time feature count (points read in place).
+__device__ __forceinline__ float pair_dist_rt(const float *__restrict__ a,
+                                              const float *__restrict__ b, int d) {
+  float t = a[0] - b[0];
+  float s = t * t;
+  for (int k = 1; k < d; ++k) {
+    t = a[k] - b[k];
+    s = __builtin_fmaf(t, t, s);
+  }
+  return __builtin_amdgcn_sqrtf(s);
+}
+
+template <int D>
+__device__ __forceinline__ void load_point(const float *__restrict__ X, int64_t ldx,
+                                           int64_t p, float (&v)[D]) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) v[k] = X[p * ldx + k];
+}
+
+// Distance of cells (i, j) read straight from X; D = 0 selects the run-time
+// feature loop.
+template <int D>
+__device__ __forceinline__ float cell_dist(const float *__restrict__ X, int64_t ldx, int d,
+                                           int64_t i, int64_t j) {
+  if constexpr (D == 0) {
+    return pair_dist_rt(X + i * ldx, X + j * ldx, d);
+  } else {
+    float a[D], b[D];
+    load_point<D>(X, ldx, i, a);
+    load_point<D>(X, ldx, j, b);
+    return pair_dist<D>(a, b);
+  }
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ uint64_t out_index(uint64_t i, uint64_t j, int64_t ldd) {
+  if constexpr (LAYOUT == kLayoutFull) {
+    return i * (uint64_t)ldd + j;
+  } else {
+    return tri64(i) + j;
+  }
+}
+
+// Launch statistics gathered by the instrumented kernels:
+// [0] blocks, [1] fully idle blocks, [2] idle threads.
+__device__ __forceinline__ void count_block(unsigned long long *counts, int live, int lanes) {
+  const int total = __syncthreads_count(live);
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    atomicAdd(&counts[0], 1ull);
+    if (total == 0) atomicAdd(&counts[1], 1ull);
+    if (lanes - total) atomicAdd(&counts[2], (unsigned long long)(lanes - total));
+  }
+}
+
+}  // namespace tdmap

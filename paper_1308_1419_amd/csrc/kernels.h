@@ -1,0 +1,36 @@
+// Host-side launchers of the tdmap kernels (internal; the public interface
+// is include/tdmap.h).  Each returns the HIP status of its launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tdmap {
+
+struct EdmArgs {
+  const float *X;
+  int64_t N;
+  int d;
+  int64_t ldx;
+  float *D;
+  int64_t ldd;
+  int layout;
+  hipStream_t stream;
+};
+
+// g(lambda) for lambda0 .. lambda0 + count - 1 (caller checks the range).
+hipError_t launch_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, hipStream_t stream);
+
+// Paper-style launch: rho x rho threads, one cell per thread.  With
+// counts != nullptr the instrumented variant counts instead of storing.
+hipError_t launch_cell(int strategy, int rho, const EdmArgs &a, unsigned long long *counts);
+
+// Coarsened tile launch (LTM on a 1D g(lambda) grid, or BB on an n x n grid).
+bool tiled_supported(int ts, int d);
+hipError_t launch_tiled(bool bb, int ts, const EdmArgs &a);
+
+// Fill n floats with a value (a kernel, not a memset, so it can sit in a
+// captured graph).
+hipError_t launch_fill(float *p, uint64_t n, float v, hipStream_t stream);
+
+}  // namespace tdmap

@@ -1,0 +1,48 @@
+// tdmap_map_blocks: g(lambda) for a range of block indices (Sec. II-A, Eq. (2)).
+#include "device.h"
+#include "kernels.h"
+
+namespace tdmap {
+
+// One lane per lambda.  Unlike the EDM kernels, lambda varies across the
+// wave here, so the fix-up compares run per lane.
+__global__ __launch_bounds__(256) void map_blocks_kernel(uint64_t lambda0, uint64_t count,
+                                                         uint32_t *__restrict__ ij) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  uint32_t i, j;
+  g_lambda((uint32_t)(lambda0 + t), i, j);
+  uint2 v;
+  v.x = i;
+  v.y = j;
+  reinterpret_cast<uint2 *>(ij)[t] = v;
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(float *__restrict__ p, uint64_t n, float v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) p[t] = v;
+}
+
+hipError_t launch_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, hipStream_t stream) {
+  // at most 2^32 lanes per launch: split the range
+  const uint64_t per_launch = (uint64_t)1 << 31;
+  for (uint64_t done = 0; done < count; done += per_launch) {
+    const uint64_t c = count - done < per_launch ? count - done : per_launch;
+    const uint32_t blocks = (uint32_t)((c + 255) / 256);
+    hipLaunchKernelGGL(map_blocks_kernel, dim3(blocks), dim3(256), 0, stream, lambda0 + done, c,
+                       ij + 2 * done);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_fill(float *p, uint64_t n, float v, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(fill_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace tdmap

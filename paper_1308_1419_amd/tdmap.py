@@ -1,0 +1,308 @@
+"""Python binding of the tdmap C ABI (include/tdmap.h).
+
+Two layers, both argument marshalling only -- every step of the work runs
+in the HIP library:
+
+* ``tdmap_*`` functions with the C names and signatures (integers for
+  pointers and streams); a non-zero status raises ``TdmapError``.
+* torch conveniences (``edm``, ``edm_backward``, ``edm_batched``,
+  ``map_blocks``, ``EDM``) that take device tensors, allocate outputs with
+  torch and pass torch's current stream.
+
+The library is loaded on first use from ``libtdmap.so`` next to this file.
+If it is missing, every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdmap.so")
+
+# enums (include/tdmap.h)
+OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = range(5)
+LTM, BB, UTM, RB, REC = range(5)
+FULL, PACKED = 0, 1
+FP32, BF16_GRAM = 0, 1
+OP_EDM, OP_BACKWARD, OP_BATCHED = 0, 1, 2
+
+STRATEGIES = {"ltm": LTM, "bb": BB, "utm": UTM, "rb": RB, "rec": REC}
+LAYOUTS = {"full": FULL, "packed": PACKED}
+PRECISIONS = {"fp32": FP32, "bf16_gram": BF16_GRAM}
+
+
+class TdmapError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = _load()
+        msg = lib.tdmap_status_string(status).decode()
+        if status == ERR_HIP:
+            msg += ": " + lib.tdmap_last_error().decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def _load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"tdmap HIP library not built: {LIB_PATH} is missing "
+            "(run python -m paper_1308_1419_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, u64, vp, sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                             ctypes.c_void_p, ctypes.c_size_t)
+    sig = {
+        "tdmap_map_blocks": ([u64, u64, vp, vp], ctypes.c_int),
+        "tdmap_edm": ([vp, i64, i32, i64, vp, i64, i32, i32, i32, i32, vp, sz, vp],
+                      ctypes.c_int),
+        "tdmap_edm_backward": ([vp, i64, i32, i64, vp, i64, i32, vp, i32, i32, vp, sz, vp],
+                               ctypes.c_int),
+        "tdmap_edm_batched": ([vp, i32, i32, vp, vp, vp, i32, vp, sz, vp], ctypes.c_int),
+        "tdmap_workspace_size": ([i32, i64, i32, i32, i32, i32], sz),
+        "tdmap_waste_counts": ([i32, i64, i32, vp], ctypes.c_int),
+        "tdmap_count_waste": ([i32, i64, i32, vp, vp], ctypes.c_int),
+        "tdmap_tuned_rho": ([i32, i32, i32, i32, i64], i32),
+        "tdmap_autotune_reset": ([], None),
+        "tdmap_status_string": ([i32], ctypes.c_char_p),
+        "tdmap_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+EXPORTED = (
+    "tdmap_map_blocks", "tdmap_edm", "tdmap_edm_backward", "tdmap_edm_batched",
+    "tdmap_workspace_size", "tdmap_waste_counts", "tdmap_count_waste",
+    "tdmap_tuned_rho", "tdmap_autotune_reset", "tdmap_status_string",
+    "tdmap_last_error",
+)
+
+
+def _check(status: int, where: str) -> None:
+    if status != OK:
+        raise TdmapError(status, where)
+
+
+# ---------------------------------------------------------------------------
+# C-named entry points
+# ---------------------------------------------------------------------------
+
+def tdmap_map_blocks(lambda0: int, count: int, ij: int, stream: int) -> None:
+    _check(_load().tdmap_map_blocks(lambda0, count, ij, stream), "tdmap_map_blocks")
+
+
+def tdmap_edm(X: int, N: int, d: int, ldx: int, D: int, ldd: int, layout: int,
+              strategy: int, rho: int, precision: int, workspace: int,
+              ws_bytes: int, stream: int) -> None:
+    _check(_load().tdmap_edm(X, N, d, ldx, D, ldd, layout, strategy, rho, precision,
+                             workspace, ws_bytes, stream), "tdmap_edm")
+
+
+def tdmap_edm_backward(X: int, N: int, d: int, ldx: int, dD: int, ldd: int,
+                       layout: int, dX: int, rho: int, deterministic: int,
+                       workspace: int, ws_bytes: int, stream: int) -> None:
+    _check(_load().tdmap_edm_backward(X, N, d, ldx, dD, ldd, layout, dX, rho,
+                                      deterministic, workspace, ws_bytes, stream),
+           "tdmap_edm_backward")
+
+
+def tdmap_edm_batched(X_cat: int, d: int, num_sets: int, point_off: int, out_off: int,
+                      D_cat: int, rho: int, workspace: int, ws_bytes: int,
+                      stream: int) -> None:
+    _check(_load().tdmap_edm_batched(X_cat, d, num_sets, point_off, out_off, D_cat, rho,
+                                     workspace, ws_bytes, stream), "tdmap_edm_batched")
+
+
+def tdmap_workspace_size(op: int, N: int, d: int, num_sets: int, rho: int, flags: int) -> int:
+    return int(_load().tdmap_workspace_size(op, N, d, num_sets, rho, flags))
+
+
+def tdmap_waste_counts(strategy: int, N: int, rho: int) -> tuple:
+    out = (ctypes.c_int64 * 3)()
+    _check(_load().tdmap_waste_counts(strategy, N, rho, ctypes.addressof(out)),
+           "tdmap_waste_counts")
+    return tuple(int(v) for v in out)
+
+
+def tdmap_count_waste(strategy: int, N: int, rho: int, counts: int, stream: int) -> None:
+    _check(_load().tdmap_count_waste(strategy, N, rho, counts, stream), "tdmap_count_waste")
+
+
+def tdmap_tuned_rho(op: int, strategy: int, layout: int, d: int, size: int) -> int:
+    return int(_load().tdmap_tuned_rho(op, strategy, layout, d, size))
+
+
+def tdmap_autotune_reset() -> None:
+    _load().tdmap_autotune_reset()
+
+
+def tdmap_status_string(status: int) -> str:
+    return _load().tdmap_status_string(status).decode()
+
+
+def tdmap_last_error() -> str:
+    return _load().tdmap_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# torch conveniences
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream() -> int:
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def _points(X):
+    torch = _torch()
+    if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32
+            and X.dim() == 2):
+        raise TypeError("X must be a 2D float32 CUDA tensor")
+    if X.stride(1) != 1:
+        raise ValueError("X must have unit stride along features")
+    return X
+
+
+def packed_size(N: int) -> int:
+    return N * (N + 1) // 2
+
+
+def map_blocks(lambda0: int, count: int, out=None):
+    """g(lambda) for lambda0 .. lambda0+count-1 as a (count, 2) int32 tensor
+    holding the uint32 (i, j) bits."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((count, 2), dtype=torch.int32, device="cuda")
+    tdmap_map_blocks(lambda0, count, out.data_ptr() if count else 0, _stream())
+    return out
+
+
+def edm(X, layout: str = "full", strategy: str = "ltm", rho: int = 0,
+        precision: str = "fp32", out=None, ldd: Optional[int] = None, workspace=None):
+    """Lower-triangular EDM of the rows of X (see tdmap_edm)."""
+    torch = _torch()
+    X = _points(X)
+    N, d = X.shape
+    lay = LAYOUTS[layout]
+    prec = PRECISIONS[precision]
+    if out is None:
+        if lay == FULL:
+            out = torch.empty((N, N), dtype=torch.float32, device=X.device)
+        else:
+            out = torch.empty(packed_size(N), dtype=torch.float32, device=X.device)
+    if ldd is None:
+        ldd = out.stride(0) if lay == FULL else 0
+    ws_bytes = tdmap_workspace_size(OP_EDM, N, d, 0, rho, prec)
+    if ws_bytes and workspace is None:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=X.device)
+    ws_ptr = workspace.data_ptr() if workspace is not None else 0
+    ws_len = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    tdmap_edm(X.data_ptr(), N, d, X.stride(0), out.data_ptr(), ldd, lay,
+              STRATEGIES[strategy], rho, prec, ws_ptr, ws_len, _stream())
+    return out
+
+
+def edm_backward(X, dD, layout: str = "packed", rho: int = 0, deterministic: bool = True,
+                 ldd: Optional[int] = None, out=None, workspace=None):
+    """dL/dX from dL/dD over the triangle (see tdmap_edm_backward)."""
+    torch = _torch()
+    X = _points(X)
+    N, d = X.shape
+    lay = LAYOUTS[layout]
+    if out is None:
+        out = torch.empty((N, d), dtype=torch.float32, device=X.device)
+    if ldd is None:
+        ldd = dD.stride(0) if lay == FULL else 0
+    det = 1 if deterministic else 0
+    ws_bytes = tdmap_workspace_size(OP_BACKWARD, N, d, 0, rho, det)
+    if ws_bytes and workspace is None:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=X.device)
+    ws_ptr = workspace.data_ptr() if workspace is not None else 0
+    ws_len = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    tdmap_edm_backward(X.data_ptr(), N, d, X.stride(0), dD.data_ptr(), ldd, lay,
+                       out.data_ptr(), rho, det, ws_ptr, ws_len, _stream())
+    return out
+
+
+def edm_batched(X_cat, point_off, out_off, rho: int = 0, out=None, workspace=None):
+    """Packed EDMs of many point sets in one launch (see tdmap_edm_batched).
+    ``point_off`` / ``out_off`` are int64 CUDA tensors of length S+1; the
+    total output size is read from ``out_off`` only when ``out`` is None."""
+    torch = _torch()
+    X_cat = _points(X_cat)
+    d = X_cat.shape[1]
+    if X_cat.stride(0) != d:
+        raise ValueError("X_cat must be contiguous")
+    S = point_off.numel() - 1
+    if out is None:
+        total = int(out_off[-1].item())
+        out = torch.empty(total, dtype=torch.float32, device=X_cat.device)
+    ws_bytes = tdmap_workspace_size(OP_BATCHED, 0, d, S, rho, 0)
+    if ws_bytes and workspace is None:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=X_cat.device)
+    ws_ptr = workspace.data_ptr() if workspace is not None else 0
+    ws_len = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    tdmap_edm_batched(X_cat.data_ptr(), d, S, point_off.data_ptr(), out_off.data_ptr(),
+                      out.data_ptr(), rho, ws_ptr, ws_len, _stream())
+    return out
+
+
+def count_waste(strategy: str, N: int, rho: int):
+    """(blocks, fully idle blocks, idle threads) counted on the device."""
+    torch = _torch()
+    counts = torch.empty(3, dtype=torch.int64, device="cuda")
+    tdmap_count_waste(STRATEGIES[strategy], N, rho, counts.data_ptr(), _stream())
+    return tuple(int(v) for v in counts.cpu().tolist())
+
+
+def waste_counts(strategy: str, N: int, rho: int):
+    """(blocks, fully idle blocks, idle threads) in closed form (host)."""
+    return tdmap_waste_counts(STRATEGIES[strategy], N, rho)
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class EDM(torch.autograd.Function):
+        """Packed lower-triangular EDM with the hand-written backward."""
+
+        @staticmethod
+        def forward(ctx, X, rho: int = 0, deterministic: bool = True):
+            ctx.save_for_backward(X)
+            ctx.rho = rho
+            ctx.deterministic = deterministic
+            return edm(X.contiguous(), layout="packed", strategy="ltm", rho=rho)
+
+        @staticmethod
+        def backward(ctx, dD):
+            (X,) = ctx.saved_tensors
+            dX = edm_backward(X.contiguous(), dD.contiguous(), layout="packed",
+                              rho=ctx.rho, deterministic=ctx.deterministic)
+            return dX, None, None
+
+    return EDM
+
+
+_EDM = None
+
+
+def EDM():
+    """The torch.autograd.Function class (built on first use)."""
+    global _EDM
+    if _EDM is None:
+        _EDM = _make_autograd()
+    return _EDM

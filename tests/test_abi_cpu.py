@@ -1,0 +1,117 @@
+"""The C ABI library on the CPU: it loads, exports every symbol the header
+declares, and its host-only logic (validation, workspace sizes, closed-form
+launch statistics) behaves as documented.  No call here reaches the GPU:
+each one returns before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import maps
+from paper_1308_1419_amd import tdmap
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tdmap.h")
+
+
+def _header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tdmap_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(tdmap.LIB_PATH):
+        pytest.fail("libtdmap.so is not built (run __graft_entry__.build())")
+    return tdmap._load()
+
+
+def test_library_exports_every_header_symbol(lib):
+    names = _header_functions()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(tdmap.EXPORTED)
+
+
+def test_status_strings(lib):
+    for s in range(5):
+        assert tdmap.tdmap_status_string(s)
+    assert tdmap.tdmap_status_string(99) == "unknown status"
+    assert tdmap.tdmap_last_error() == ""
+
+
+def test_validation_rejects_before_launch(lib):
+    L = tdmap._load()
+    # NULL X / D with N > 0
+    assert L.tdmap_edm(None, 10, 3, 3, None, 10, 0, 0, 16, 0, None, 0, None) == tdmap.ERR_INVALID
+    # N < 0, d < 1, ldx < d
+    assert L.tdmap_edm(8, -1, 3, 3, 8, 10, 0, 0, 16, 0, None, 0, None) == tdmap.ERR_INVALID
+    assert L.tdmap_edm(8, 10, 0, 3, 8, 10, 0, 0, 16, 0, None, 0, None) == tdmap.ERR_INVALID
+    assert L.tdmap_edm(8, 10, 3, 2, 8, 10, 0, 0, 16, 0, None, 0, None) == tdmap.ERR_INVALID
+    # ldd < N for the full layout; unknown layout / strategy / rho
+    assert L.tdmap_edm(8, 10, 3, 3, 8, 9, 0, 0, 16, 0, None, 0, None) == tdmap.ERR_INVALID
+    assert L.tdmap_edm(8, 10, 3, 3, 8, 10, 7, 0, 16, 0, None, 0, None) == tdmap.ERR_INVALID
+    assert L.tdmap_edm(8, 10, 3, 3, 8, 10, 0, 9, 16, 0, None, 0, None) == tdmap.ERR_INVALID
+    assert L.tdmap_edm(8, 10, 3, 3, 8, 10, 0, 0, 12, 0, None, 0, None) == tdmap.ERR_INVALID
+    # tiled rho only for LTM / BB, d <= 4
+    assert L.tdmap_edm(8, 10, 3, 3, 8, 10, 0, tdmap.RB, 128, 0, None, 0, None) == tdmap.ERR_UNSUPPORTED
+    assert L.tdmap_edm(8, 10, 5, 5, 8, 10, 0, 0, 128, 0, None, 0, None) == tdmap.ERR_UNSUPPORTED
+    # N = 0 is a no-op even with NULL buffers
+    assert L.tdmap_edm(None, 0, 3, 3, None, 0, 0, 0, 16, 0, None, 0, None) == tdmap.OK
+    # the map: NULL output, and a range past 2^32
+    assert L.tdmap_map_blocks(0, 10, None, None) == tdmap.ERR_INVALID
+    assert L.tdmap_map_blocks((1 << 32) - 5, 6, 8, None) == tdmap.ERR_UNSUPPORTED
+    assert L.tdmap_map_blocks(5, 0, None, None) == tdmap.OK
+    # UTM's thread index is 32-bit: N(N+1)/2 must stay below 2^32
+    assert L.tdmap_edm(8, 100000, 3, 3, 8, 100000, 0, tdmap.UTM, 16, 0, None, 0, None) \
+        == tdmap.ERR_UNSUPPORTED
+    # the instrumented count needs a paper-style rho
+    assert L.tdmap_count_waste(0, 100, 64, 8, None) == tdmap.ERR_UNSUPPORTED
+    assert L.tdmap_count_waste(0, 100, 16, None, None) == tdmap.ERR_INVALID
+
+
+def test_fp32_needs_no_workspace(lib):
+    for rho in (0, 8, 16, 32, 64, 128, 256):
+        assert tdmap.tdmap_workspace_size(tdmap.OP_EDM, 30000, 3, 0, rho, tdmap.FP32) == 0
+
+
+@pytest.mark.parametrize("strategy", ["ltm", "bb", "utm", "rb", "rec"])
+def test_closed_form_waste_matches_oracle_enumeration(lib, strategy):
+    for N in [1, 2, 5, 16, 17, 31, 64, 65, 100, 129]:
+        for rho in [1, 2, 3, 8, 16]:
+            e = maps.enumerate_waste(strategy, N, rho)
+            got = tdmap.waste_counts(strategy, N, rho)
+            assert got == (e["blocks"], e["idle_blocks"], e["idle_lanes"]), (N, rho)
+
+
+@pytest.mark.parametrize("strategy", ["ltm", "bb", "utm", "rb", "rec"])
+def test_closed_form_waste_matches_oracle_at_benchmark_sizes(lib, strategy):
+    for N in [1024, 30000, 30720]:
+        for rho in [8, 16, 32]:
+            c = maps.waste_closed_form(strategy, N, rho)
+            got = tdmap.waste_counts(strategy, N, rho)
+            assert got == (c["blocks"], c["idle_blocks"], c["idle_lanes"]), (N, rho)
+
+
+def test_waste_counts_invalid(lib):
+    out = (ctypes.c_int64 * 3)()
+    L = tdmap._load()
+    assert L.tdmap_waste_counts(9, 10, 16, ctypes.addressof(out)) == tdmap.ERR_INVALID
+    assert L.tdmap_waste_counts(0, 10, 0, ctypes.addressof(out)) == tdmap.ERR_INVALID
+    assert L.tdmap_waste_counts(0, 10, 16, None) == tdmap.ERR_INVALID
+
+
+def test_product_path_never_imports_oracle():
+    # the binding and the HIP sources must not import, load or include
+    # anything from oracle/
+    pkg = os.path.join(ROOT, "paper_1308_1419_amd")
+    pat = re.compile(r"(^\s*(from|import)\s+oracle\b)|liboracle|oracle/|#include.*oracle",
+                     re.M)
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not pat.search(text), f

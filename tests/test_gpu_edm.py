@@ -1,0 +1,308 @@
+"""GPU parity of the block map and the forward EDM against the CPU oracle.
+
+All calls go through the C ABI (ctypes binding).  Bars:
+* g(lambda): bit-exact with the exact-integer oracle;
+* FP32 distances: |D_gpu - D_64| <= 1e-6 D_64 per cell and D_gpu == 0 where
+  D_64 == 0;
+* every strategy writes every cell j <= i and nothing else (an output
+  pre-filled with a sentinel keeps it above the diagonal), and all
+  strategies agree bit for bit (one per-pair function);
+* device-counted launch statistics equal the oracle's closed forms.
+"""
+import numpy as np
+import pytest
+
+from oracle import edm as oedm
+from oracle import maps as omaps
+from oracle import native
+from paper_1308_1419_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1308_1419_amd import tdmap  # noqa: E402
+
+SENTINEL = np.int32(0x7FC0DEAD)  # a NaN payload no kernel produces
+REL = oedm.fp32_rel_tol()
+STRATS = ["ltm", "bb", "utm", "rb", "rec"]
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test collected on a machine without a GPU")
+
+
+def _full_sentinel(N, ld=None):
+    ld = ld or N
+    buf = torch.empty((N, ld), dtype=torch.float32, device="cuda")
+    buf.view(torch.int32).fill_(int(SENTINEL))
+    return buf
+
+
+def _check_rel(got, ref, where=""):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert got.shape == ref.shape, where
+    zero = ref == 0
+    assert np.all(got[zero] == 0), f"{where}: non-zero where the exact distance is 0"
+    err = np.abs(got - ref)
+    bad = err > REL * ref
+    if np.any(bad):
+        k = int(np.argmax(err / np.where(ref > 0, ref, 1)))
+        raise AssertionError(f"{where}: {int(bad.sum())} cells out of tolerance, worst "
+                             f"at {k}: got {got.flat[k]!r} ref {ref.flat[k]!r}")
+
+
+def _check_full(D, X, ld=None):
+    """Lower triangle vs the FP64 oracle, upper triangle untouched."""
+    N = X.shape[0]
+    Dh = D.cpu().numpy()
+    ref = oedm.edm64_full(X)
+    lower = np.tril(np.ones((N, N), dtype=bool))
+    _check_rel(Dh[:, :N][lower], ref[lower], "lower")
+    upper_bits = Dh.view(np.int32)[:, :N][~lower]
+    assert np.all(upper_bits == SENTINEL), "a cell above the diagonal was written"
+    if ld and ld > N:
+        assert np.all(Dh.view(np.int32)[:, N:] == SENTINEL), "padding written"
+
+
+# --------------------------------------------------------------------------
+# g(lambda)
+# --------------------------------------------------------------------------
+
+def test_map_blocks_exact_below_2_16():
+    _require_gpu()
+    count = 1 << 16
+    ij = tdmap.map_blocks(0, count).cpu().numpy().astype(np.int64)
+    ref = np.array(omaps.g_enumerate(count), dtype=np.int64)
+    assert np.array_equal(ij, ref)
+
+
+def test_map_blocks_row_boundaries_exact():
+    _require_gpu()
+    # every row start below 2^32 and its two neighbours, in a few launches
+    rows = np.arange(1, 92682, dtype=np.int64)
+    starts = rows * (rows + 1) // 2
+    for i in list(range(1, 2000)) + list(range(46000, 46400)) + list(range(92000, 92682)):
+        t = int(starts[i - 1])
+        ij = tdmap.map_blocks(t - 1, 3).cpu().numpy().astype(np.int64)
+        assert tuple(ij[0]) == omaps.g_oracle(t - 1)
+        assert tuple(ij[1]) == omaps.g_oracle(t) == (i, 0)
+        assert tuple(ij[2]) == omaps.g_oracle(t + 1)
+
+
+def test_map_blocks_whole_32bit_range_by_succession():
+    # all of [0, 2^32): each chunk starts at the oracle's value and every
+    # step goes to the next cell of the row-major triangle
+    _require_gpu()
+    chunk = 1 << 27
+    out = torch.empty((chunk, 2), dtype=torch.int32, device="cuda")
+    for c in range((1 << 32) // chunk):
+        lam0 = c * chunk
+        tdmap.map_blocks(lam0, chunk, out=out)
+        i = out[:, 0].to(torch.int64)
+        j = out[:, 1].to(torch.int64)
+        assert (int(i[0]), int(j[0])) == omaps.g_oracle(lam0)
+        same_row = (i[1:] == i[:-1]) & (j[1:] == j[:-1] + 1)
+        next_row = (i[1:] == i[:-1] + 1) & (j[1:] == 0) & (j[:-1] == i[:-1])
+        assert bool(torch.all(same_row | next_row)), f"chunk {c}"
+        assert bool(torch.all(j <= i))
+        last = lam0 + chunk - 1
+        assert (int(i[-1]), int(j[-1])) == omaps.g_oracle(last)
+    torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------
+# EDM, paper-style launches
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("rho", [8, 16, 32])
+@pytest.mark.parametrize("N", [1, 2, 31, 1000, 1037])
+def test_edm_cell_strategies_full(strategy, rho, N):
+    _require_gpu()
+    X = synth.uniform_points(N, 3, seed=100 + N)
+    Xd = torch.from_numpy(X).cuda()
+    D = _full_sentinel(N)
+    tdmap.edm(Xd, layout="full", strategy=strategy, rho=rho, out=D)
+    torch.cuda.synchronize()
+    _check_full(D, X)
+
+
+@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 7])
+def test_edm_cell_strategies_packed_features(strategy, d):
+    _require_gpu()
+    N = 517
+    X = synth.uniform_points(N, d, seed=7 * d)
+    Xd = torch.from_numpy(X).cuda()
+    D = tdmap.edm(Xd, layout="packed", strategy=strategy, rho=16)
+    torch.cuda.synchronize()
+    _check_rel(D.cpu().numpy(), oedm.edm64_packed(X), f"{strategy} d={d}")
+
+
+def test_edm_config_small_ltm_vs_bb_bitwise():
+    # the 1024-point workload: LTM and BB with 16x16 blocks, full output
+    _require_gpu()
+    X = synth.uniform_points(1024, 3, seed=synth.workload_seed(1))
+    Xd = torch.from_numpy(X).cuda()
+    outs = {}
+    for s in STRATS:
+        D = _full_sentinel(1024)
+        tdmap.edm(Xd, layout="full", strategy=s, rho=16, out=D)
+        outs[s] = D
+    torch.cuda.synchronize()
+    _check_full(outs["ltm"], X)
+    for s in STRATS[1:]:
+        assert torch.equal(outs[s].view(torch.int32), outs["ltm"].view(torch.int32)), s
+
+
+def test_edm_pitched_input_and_output():
+    _require_gpu()
+    N, d = 300, 3
+    Xbig = synth.uniform_points(N, 8, seed=77)
+    Xd = torch.from_numpy(Xbig).cuda()[:, :d]  # ldx = 8
+    X = np.ascontiguousarray(Xbig[:, :d])
+    for s in STRATS:
+        D = _full_sentinel(N, ld=N + 13)
+        tdmap.edm(Xd, layout="full", strategy=s, rho=16, out=D, ldd=N + 13)
+        torch.cuda.synchronize()
+        _check_full(D, X, ld=N + 13)
+
+
+def test_edm_coincident_points_are_zero():
+    _require_gpu()
+    X = synth.uniform_points(200, 3, seed=5)
+    X[50] = X[10]
+    X[199] = X[0]
+    Xd = torch.from_numpy(X).cuda()
+    for s in STRATS:
+        D = tdmap.edm(Xd, layout="packed", strategy=s, rho=8)
+        torch.cuda.synchronize()
+        Dh = D.cpu().numpy()
+        assert Dh[oedm.tri(50) + 10] == 0.0 and Dh[oedm.tri(199) + 0] == 0.0
+        for i in range(200):
+            assert Dh[oedm.tri(i) + i] == 0.0
+
+
+# --------------------------------------------------------------------------
+# EDM, coarsened tiles (LTM and BB)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("strategy", ["ltm", "bb"])
+@pytest.mark.parametrize("rho", [64, 128, 256])
+@pytest.mark.parametrize("N", [1, 5, 64, 300, 1037])
+def test_edm_tiled_full(strategy, rho, N):
+    _require_gpu()
+    X = synth.uniform_points(N, 3, seed=200 + N)
+    Xd = torch.from_numpy(X).cuda()
+    D = _full_sentinel(N)
+    tdmap.edm(Xd, layout="full", strategy=strategy, rho=rho, out=D)
+    torch.cuda.synchronize()
+    _check_full(D, X)
+    # bitwise equal to the paper-style LTM launch
+    R = _full_sentinel(N)
+    tdmap.edm(Xd, layout="full", strategy="ltm", rho=16, out=R)
+    assert torch.equal(D.view(torch.int32), R.view(torch.int32))
+
+
+@pytest.mark.parametrize("strategy", ["ltm", "bb"])
+@pytest.mark.parametrize("rho", [64, 128, 256])
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_edm_tiled_packed_and_unaligned(strategy, rho, d):
+    _require_gpu()
+    N = 777
+    X = synth.uniform_points(N, d, seed=300 + d)
+    Xd = torch.from_numpy(X).cuda()
+    D = tdmap.edm(Xd, layout="packed", strategy=strategy, rho=rho)
+    torch.cuda.synchronize()
+    _check_rel(D.cpu().numpy(), oedm.edm64_packed(X), f"packed {strategy} {rho} d={d}")
+    # full layout with a pitch that is not a multiple of 4: scalar stores
+    F = _full_sentinel(N, ld=N + 1)
+    tdmap.edm(Xd, layout="full", strategy=strategy, rho=rho, out=F, ldd=N + 1)
+    torch.cuda.synchronize()
+    _check_full(F, X, ld=N + 1)
+
+
+def test_edm_autotuned_matches():
+    _require_gpu()
+    tdmap.tdmap_autotune_reset()
+    N = 2000
+    X = synth.uniform_points(N, 3, seed=9)
+    Xd = torch.from_numpy(X).cuda()
+    D = _full_sentinel(N)
+    tdmap.edm(Xd, layout="full", strategy="ltm", rho=0, out=D)
+    torch.cuda.synchronize()
+    ts = tdmap.tdmap_tuned_rho(tdmap.OP_EDM, tdmap.LTM, tdmap.FULL, 3, N)
+    assert ts in (64, 128, 256)
+    _check_full(D, X)
+
+
+# --------------------------------------------------------------------------
+# the 30000-point workload at the benchmark's launch configurations
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def big():
+    _require_gpu()
+    N = 30000
+    X = synth.uniform_points(N, 3, seed=synth.workload_seed(2))
+    Xd = torch.from_numpy(X).cuda()
+    ref = _full_sentinel(N)
+    tdmap.edm(Xd, layout="full", strategy="ltm", rho=0, out=ref)
+    torch.cuda.synchronize()
+    return X, Xd, ref
+
+
+def test_big_sampled_rows_against_oracle(big):
+    X, Xd, ref = big
+    N = X.shape[0]
+    rows = synth.sample_rows(N, 96, seed=5)
+    rows += [127, 128, 255, 256, 29951, 29952]  # tile boundaries and the ragged edge
+    rows = sorted(set(rows))
+    exp = native.edm_rows(X, rows)
+    idx = torch.as_tensor(rows, device="cuda")
+    got = ref.index_select(0, idx).cpu().numpy()
+    for r, i in enumerate(rows):
+        _check_rel(got[r, : i + 1], exp[r], f"row {i}")
+        assert np.all(got[r].view(np.int32)[i + 1:] == SENTINEL), f"row {i} upper"
+
+
+def test_big_upper_triangle_untouched(big):
+    X, Xd, ref = big
+    N = X.shape[0]
+    cols = torch.arange(N, device="cuda")
+    bits = ref.view(torch.int32)
+    for r0 in range(0, N, 2000):
+        rows = torch.arange(r0, min(N, r0 + 2000), device="cuda")
+        upper = cols[None, :] > rows[:, None]
+        band = bits[r0: r0 + rows.numel()]
+        assert bool(torch.all(band[upper] == int(SENTINEL)))
+        assert not bool(torch.any(band[~upper] == int(SENTINEL)))
+
+
+@pytest.mark.parametrize("strategy", STRATS)
+def test_big_strategies_bitwise_equal(big, strategy):
+    X, Xd, ref = big
+    N = X.shape[0]
+    rhos = [8, 16, 32] + ([64, 128, 256] if strategy in ("ltm", "bb") else [])
+    D = torch.empty_like(ref)
+    for rho in rhos:
+        D.view(torch.int32).fill_(int(SENTINEL))
+        tdmap.edm(Xd, layout="full", strategy=strategy, rho=rho, out=D)
+        torch.cuda.synchronize()
+        assert torch.equal(D.view(torch.int32), ref.view(torch.int32)), (strategy, rho)
+
+
+# --------------------------------------------------------------------------
+# wasted blocks counted on the device
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("N,rho", [(1, 8), (1000, 8), (1037, 16), (3000, 32), (30000, 16),
+                                   (30000, 32)])
+def test_device_waste_counts_match_oracle(strategy, N, rho):
+    _require_gpu()
+    got = tdmap.count_waste(strategy, N, rho)
+    c = omaps.waste_closed_form(strategy, N, rho)
+    assert got == (c["blocks"], c["idle_blocks"], c["idle_lanes"])
