@@ -110,7 +110,19 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--only-main", action="store_true",
                     help="time only the main step (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy three times (scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 3 x 2^30 bytes")
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
               "(the EDM path runs on a single device)", file=sys.stderr)
