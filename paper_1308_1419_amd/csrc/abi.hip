@@ -227,12 +227,16 @@ int tdmap_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, void *strea
 
 size_t tdmap_workspace_size(int32_t op, int64_t N, int32_t d, int32_t num_sets, int32_t rho,
                             int32_t flags) {
-  (void)N;
-  (void)d;
   (void)num_sets;
-  (void)rho;
-  (void)flags;
+  if (N < 0 || d < 1) return 0;
   switch (op) {
+    case TDMAP_OP_BACKWARD:
+      if (!flags || d > 4) return 0;
+      if (rho == 0)
+        return std::max(tdmap::backward_workspace_bytes(N, d, 64),
+                        tdmap::backward_workspace_bytes(N, d, 128));
+      if (rho != 64 && rho != 128) return 0;
+      return tdmap::backward_workspace_bytes(N, d, rho);
     default:
       return 0;
   }
@@ -285,9 +289,34 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int64
 int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx, const float *dD,
                        int64_t ldd, int32_t layout, float *dX, int32_t rho, int32_t deterministic,
                        void *workspace, size_t ws_bytes, void *stream) {
-  (void)X; (void)N; (void)d; (void)ldx; (void)dD; (void)ldd; (void)layout; (void)dX; (void)rho;
-  (void)deterministic; (void)workspace; (void)ws_bytes; (void)stream;
-  return TDMAP_ERR_UNSUPPORTED;
+  int st = validate_edm_common(X, N, d, ldx, dD, ldd, layout);
+  if (st != TDMAP_OK) return st;
+  if (N > 0 && dX == nullptr) return TDMAP_ERR_INVALID;
+  if (rho != 0 && rho != 64 && rho != 128) return TDMAP_ERR_INVALID;
+  if (d > 4) return TDMAP_ERR_UNSUPPORTED;
+  if (N == 0) return TDMAP_OK;
+  const uint64_t nb = ceil_div((uint64_t)N, rho ? (uint64_t)rho : 64);
+  if (tri(nb) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
+  const bool det = deterministic != 0;
+  if (det) {
+    const size_t need = tdmap_workspace_size(TDMAP_OP_BACKWARD, N, d, 0, rho, 1);
+    if (workspace == nullptr || ws_bytes < need) return TDMAP_ERR_WORKSPACE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  tdmap::BwdArgs a{X, N, d, ldx, dD, ldd, layout, dX,
+                   det ? reinterpret_cast<float *>(workspace) : nullptr, s};
+  int ts = rho;
+  if (ts == 0) {
+    const TuneKey key(TDMAP_OP_BACKWARD, 0, 0, d, size_bucket(N));
+    ts = tuned_lookup(key);
+    if (ts == 0) {
+      ts = autotune({64, 128}, s, [&](int c) { return tdmap::launch_backward(c, a); }, &st);
+      if (st != TDMAP_OK) return st;
+      tuned_store(key, ts);
+    }
+  }
+  TD_HIP(tdmap::launch_backward(ts, a), "tdmap_edm_backward");
+  return TDMAP_OK;
 }
 
 int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets, const int64_t *point_off,

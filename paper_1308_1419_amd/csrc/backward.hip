@@ -1,0 +1,200 @@
+// Gradient through the lower-triangular EDM, over the same g(lambda) tiles
+// as the forward map.
+//
+// For a cell (i, j), j < i, with g = dL/dD_ij and diff = x_i - x_j:
+//   c = g / ||diff|| = g * rsq(||diff||^2)   (0 when ||diff|| = 0)
+//   dX_i += c * diff,   dX_j -= c * diff.
+// A 256-thread work-group owns a TS x TS tile (I, J) = g(lambda).  Lanes map
+// to columns (TS / 64 per lane) so every dD row segment is read with
+// coalesced 4-byte loads; waves split the rows.  Column sums stay in
+// registers; each row sum is reduced across the wave.  Per-tile partial
+// sums then either go to a workspace (deterministic: a second kernel adds
+// them in a fixed order) or are added to dX with atomics.
+#include "device.h"
+#include "kernels.h"
+
+namespace tdmap {
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+template <int TS, int D, int LAYOUT, bool DET>
+__global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
+  const uint32_t lam = lam0 + blockIdx.x;
+  uint32_t I, J;
+  g_lambda(lam, I, J);
+  constexpr int CPL = TS / 64;  // columns per lane
+  constexpr int RPW = TS / 4;   // rows per wave
+  const int t = threadIdx.x;
+  const int w = t >> 6;
+  const int l = t & 63;
+  const int64_t N = a.N;
+  const int64_t row0 = (int64_t)I * TS;
+  const int64_t col0 = (int64_t)J * TS;
+
+  __shared__ float xs[TS * D];
+  __shared__ float rowp[TS * D];
+  __shared__ float colp[4][TS * D];
+
+  for (int e = t; e < TS * D; e += 256) {
+    const int r = e / D;
+    const int k = e - r * D;
+    const int64_t p = row0 + r;
+    xs[e] = p < N ? a.X[p * a.ldx + k] : 0.0f;
+  }
+  float xj[CPL][D];
+  bool jok[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    const int64_t j = col0 + l + 64 * c;
+    jok[c] = j < N;
+#pragma unroll
+    for (int k = 0; k < D; ++k) xj[c][k] = jok[c] ? a.X[j * a.ldx + k] : 0.0f;
+  }
+  float cacc[CPL][D];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c)
+#pragma unroll
+    for (int k = 0; k < D; ++k) cacc[c][k] = 0.0f;
+  __syncthreads();
+
+  const bool diag = I == J;
+  for (int rr = 0; rr < RPW; ++rr) {
+    const int r = rr * 4 + w;
+    const int64_t i = row0 + r;
+    float rs[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) rs[k] = 0.0f;
+    if (i < N) {
+      float xi[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) xi[k] = xs[r * D + k];
+      const uint64_t base = out_index<LAYOUT>((uint64_t)i, (uint64_t)col0, a.ldd);
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int64_t j = col0 + l + 64 * c;
+        const bool ok = jok[c] && (!diag || j < i);
+        const float g = ok ? a.dD[base + l + 64 * c] : 0.0f;
+        float diff[D];
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          diff[k] = xi[k] - xj[c][k];
+          s = __builtin_fmaf(diff[k], diff[k], s);
+        }
+        const float cc = (ok && s > 0.0f) ? g * __builtin_amdgcn_rsqf(s) : 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const float v = cc * diff[k];
+          rs[k] += v;
+          cacc[c][k] -= v;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) rs[k] = wave_sum(rs[k]);
+    if (l == 0) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) rowp[r * D + k] = rs[k];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c)
+#pragma unroll
+    for (int k = 0; k < D; ++k) colp[w][(l + 64 * c) * D + k] = cacc[c][k];
+  __syncthreads();
+
+  for (int e = t; e < TS * D; e += 256) {
+    const float cs = ((colp[0][e] + colp[1][e]) + colp[2][e]) + colp[3][e];
+    if constexpr (DET) {
+      float *dst = a.ws + (uint64_t)lam * 2 * TS * D;
+      dst[e] = rowp[e];
+      dst[TS * D + e] = cs;
+    } else {
+      const int r = e / D;
+      const int k = e - r * D;
+      if (row0 + r < N) atomicAdd(&a.dX[(row0 + r) * D + k], rowp[e]);
+      if (col0 + r < N) atomicAdd(&a.dX[(col0 + r) * D + k], cs);
+    }
+  }
+}
+
+// Deterministic second pass: point p in block B = p / TS collects the row
+// partials of tiles (B, 0..B) and the column partials of tiles (B..nb-1, B),
+// in that order.
+template <int TS, int D>
+__global__ __launch_bounds__(TS * D) void edm_bwd_reduce(const float *__restrict__ ws,
+                                                         float *__restrict__ dX, int64_t N,
+                                                         uint32_t nb) {
+  const uint32_t B = blockIdx.x;
+  const int e = threadIdx.x;
+  const int64_t p = (int64_t)B * TS + e / D;
+  if (p >= N) return;
+  constexpr int STRIDE = 2 * TS * D;
+  float acc = 0.0f;
+  const uint64_t tb = tri64(B);
+  for (uint32_t j = 0; j <= B; ++j) acc += ws[(tb + j) * STRIDE + e];
+  for (uint32_t i = B; i < nb; ++i) acc += ws[(tri64(i) + B) * STRIDE + TS * D + e];
+  dX[(uint64_t)B * TS * D + e] = acc;
+}
+
+template <int TS, int D, int LAYOUT, bool DET>
+static hipError_t launch_bwd_t(const BwdArgs &a) {
+  const uint64_t nb = (uint64_t)((a.N + TS - 1) / TS);
+  const uint64_t T = nb * (nb + 1) / 2;
+  hipError_t e;
+  if (!DET) {
+    if ((e = launch_fill(a.dX, (uint64_t)a.N * D, 0.0f, a.stream)) != hipSuccess) return e;
+  }
+  const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
+  for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
+    const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
+    hipLaunchKernelGGL((edm_bwd_tile<TS, D, LAYOUT, DET>), dim3((uint32_t)c), dim3(256), 0, a.stream,
+                       a, (uint32_t)l0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (DET) {
+    hipLaunchKernelGGL((edm_bwd_reduce<TS, D>), dim3((uint32_t)nb), dim3(TS * D), 0, a.stream,
+                       a.ws, a.dX, a.N, (uint32_t)nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int TS, int D>
+static hipError_t launch_bwd_d(const BwdArgs &a) {
+  if (a.layout == kLayoutFull)
+    return a.ws ? launch_bwd_t<TS, D, kLayoutFull, true>(a) : launch_bwd_t<TS, D, kLayoutFull, false>(a);
+  return a.ws ? launch_bwd_t<TS, D, kLayoutPacked, true>(a)
+              : launch_bwd_t<TS, D, kLayoutPacked, false>(a);
+}
+
+template <int TS>
+static hipError_t launch_bwd_ts(const BwdArgs &a) {
+  switch (a.d) {
+    case 1: return launch_bwd_d<TS, 1>(a);
+    case 2: return launch_bwd_d<TS, 2>(a);
+    case 3: return launch_bwd_d<TS, 3>(a);
+    case 4: return launch_bwd_d<TS, 4>(a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t backward_workspace_bytes(int64_t N, int d, int ts) {
+  const uint64_t nb = (uint64_t)((N + ts - 1) / ts);
+  return (size_t)(nb * (nb + 1) / 2) * 2 * (size_t)ts * (size_t)d * sizeof(float);
+}
+
+hipError_t launch_backward(int ts, const BwdArgs &a) {
+  if (a.N == 0) return hipSuccess;
+  switch (ts) {
+    case 64: return launch_bwd_ts<64>(a);
+    case 128: return launch_bwd_ts<128>(a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace tdmap

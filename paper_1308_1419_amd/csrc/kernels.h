@@ -29,6 +29,23 @@ hipError_t launch_cell(int strategy, int rho, const EdmArgs &a, unsigned long lo
 bool tiled_supported(int ts, int d);
 hipError_t launch_tiled(bool bb, int ts, const EdmArgs &a);
 
+struct BwdArgs {
+  const float *X;
+  int64_t N;
+  int d;
+  int64_t ldx;
+  const float *dD;
+  int64_t ldd;
+  int layout;
+  float *dX;
+  float *ws;  // per-tile partial sums (deterministic mode), else nullptr
+  hipStream_t stream;
+};
+
+// Backward over g(lambda) tiles of edge ts (64 or 128); d in 1..4.
+size_t backward_workspace_bytes(int64_t N, int d, int ts);
+hipError_t launch_backward(int ts, const BwdArgs &a);
+
 // Fill n floats with a value (a kernel, not a memset, so it can sit in a
 // captured graph).
 hipError_t launch_fill(float *p, uint64_t n, float v, hipStream_t stream);
