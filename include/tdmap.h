@@ -147,11 +147,12 @@ int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx,
  *   point_off  device, S+1 int64, non-decreasing, point_off[0] = 0.
  *   out_off    device, S+1 int64, out_off[s+1] - out_off[s] =
  *              n_s(n_s+1)/2 with n_s = point_off[s+1] - point_off[s].
- *   rho        tile edge 16, 32, 64 or 128; 0 = autotuned.
+ *   rho        tile edge 64 or 128; 0 = autotuned.
  *   workspace  device, tdmap_workspace_size(TDMAP_OP_BATCHED, 0, d, S, rho, 0)
  *              bytes.
- * The offsets are not read on the host; inconsistent offsets are undefined
- * behaviour.  d must be 1..4.  Errors as for tdmap_edm.
+ * The offsets are not read on the host (so X_cat and D_cat must be non-NULL
+ * whenever num_sets > 0, even if every set is empty); inconsistent offsets
+ * are undefined behaviour.  d must be 1..4.  Errors as for tdmap_edm.
  */
 int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets,
                       const int64_t *point_off, const int64_t *out_off,

@@ -227,7 +227,6 @@ int tdmap_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, void *strea
 
 size_t tdmap_workspace_size(int32_t op, int64_t N, int32_t d, int32_t num_sets, int32_t rho,
                             int32_t flags) {
-  (void)num_sets;
   if (N < 0 || d < 1) return 0;
   switch (op) {
     case TDMAP_OP_BACKWARD:
@@ -237,6 +236,9 @@ size_t tdmap_workspace_size(int32_t op, int64_t N, int32_t d, int32_t num_sets, 
                         tdmap::backward_workspace_bytes(N, d, 128));
       if (rho != 64 && rho != 128) return 0;
       return tdmap::backward_workspace_bytes(N, d, rho);
+    case TDMAP_OP_BATCHED:
+      if (num_sets < 0) return 0;
+      return (size_t)(num_sets + 1) * sizeof(uint64_t);
     default:
       return 0;
   }
@@ -322,9 +324,30 @@ int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx, const 
 int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets, const int64_t *point_off,
                       const int64_t *out_off, float *D_cat, int32_t rho, void *workspace,
                       size_t ws_bytes, void *stream) {
-  (void)X_cat; (void)d; (void)num_sets; (void)point_off; (void)out_off; (void)D_cat; (void)rho;
-  (void)workspace; (void)ws_bytes; (void)stream;
-  return TDMAP_ERR_UNSUPPORTED;
+  if (num_sets < 0 || d < 1) return TDMAP_ERR_INVALID;
+  if (rho != 0 && rho != 64 && rho != 128) return TDMAP_ERR_INVALID;
+  if (num_sets == 0) return TDMAP_OK;
+  if (X_cat == nullptr || point_off == nullptr || out_off == nullptr || D_cat == nullptr)
+    return TDMAP_ERR_INVALID;
+  if (d > 4) return TDMAP_ERR_UNSUPPORTED;
+  const size_t need = tdmap_workspace_size(TDMAP_OP_BATCHED, 0, d, num_sets, rho, 0);
+  if (workspace == nullptr || ws_bytes < need) return TDMAP_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  tdmap::BatchArgs a{X_cat, d, num_sets, point_off, out_off, D_cat,
+                     reinterpret_cast<uint64_t *>(workspace), s};
+  int ts = rho;
+  int st = TDMAP_OK;
+  if (ts == 0) {
+    const TuneKey key(TDMAP_OP_BATCHED, 0, 0, d, size_bucket(num_sets));
+    ts = tuned_lookup(key);
+    if (ts == 0) {
+      ts = autotune({64, 128}, s, [&](int c) { return tdmap::launch_batched(c, a); }, &st);
+      if (st != TDMAP_OK) return st;
+      tuned_store(key, ts);
+    }
+  }
+  TD_HIP(tdmap::launch_batched(ts, a), "tdmap_edm_batched");
+  return TDMAP_OK;
 }
 
 int tdmap_waste_counts(int32_t strategy, int64_t N, int32_t rho, int64_t out[3]) {

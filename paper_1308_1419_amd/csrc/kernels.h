@@ -46,6 +46,20 @@ struct BwdArgs {
 size_t backward_workspace_bytes(int64_t N, int d, int ts);
 hipError_t launch_backward(int ts, const BwdArgs &a);
 
+struct BatchArgs {
+  const float *X;          // concatenated points, pitch d
+  int d;
+  int32_t num_sets;
+  const int64_t *point_off;
+  const int64_t *out_off;
+  float *D;
+  uint64_t *blk_off;       // workspace: num_sets + 1 tile-count prefix sums
+  hipStream_t stream;
+};
+
+// One prefix-sum launch plus one persistent launch; ts is 64 or 128.
+hipError_t launch_batched(int ts, const BatchArgs &a);
+
 // Fill n floats with a value (a kernel, not a memset, so it can sit in a
 // captured graph).
 hipError_t launch_fill(float *p, uint64_t n, float v, hipStream_t stream);
