@@ -229,6 +229,9 @@ size_t tdmap_workspace_size(int32_t op, int64_t N, int32_t d, int32_t num_sets, 
                             int32_t flags) {
   if (N < 0 || d < 1) return 0;
   switch (op) {
+    case TDMAP_OP_EDM:
+      if (flags != TDMAP_BF16_GRAM) return 0;
+      return tdmap::gram_workspace_bytes(N, d);
     case TDMAP_OP_BACKWARD:
       if (!flags || d > 4) return 0;
       if (rho == 0)
@@ -247,15 +250,22 @@ size_t tdmap_workspace_size(int32_t op, int64_t N, int32_t d, int32_t num_sets, 
 int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int64_t ldd,
               int32_t layout, int32_t strategy, int32_t rho, int32_t precision, void *workspace,
               size_t ws_bytes, void *stream) {
-  (void)workspace;
-  (void)ws_bytes;
   int st = validate_edm_common(X, N, d, ldx, D, ldd, layout);
   if (st != TDMAP_OK) return st;
   if (strategy < TDMAP_LTM || strategy > TDMAP_REC) return TDMAP_ERR_INVALID;
   if (precision != TDMAP_FP32 && precision != TDMAP_BF16_GRAM) return TDMAP_ERR_INVALID;
-  if (precision == TDMAP_BF16_GRAM) return TDMAP_ERR_UNSUPPORTED;
   if (!(rho == 0 || is_cell_rho(rho) || rho == 64 || rho == 128 || rho == 256))
     return TDMAP_ERR_INVALID;
+  if (precision == TDMAP_BF16_GRAM) {
+    if (strategy != TDMAP_LTM || layout != TDMAP_PACKED || (rho != 0 && rho != 128))
+      return TDMAP_ERR_UNSUPPORTED;
+    if (N == 0) return TDMAP_OK;
+    if (tri(ceil_div((uint64_t)N, 128)) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
+    if (workspace == nullptr || ws_bytes < tdmap::gram_workspace_bytes(N, d))
+      return TDMAP_ERR_WORKSPACE;
+    TD_HIP(tdmap::launch_gram(X, N, d, ldx, D, workspace, (hipStream_t)stream), "tdmap_edm");
+    return TDMAP_OK;
+  }
   const bool tiled = !is_cell_rho(rho);
   if (tiled && strategy != TDMAP_LTM && strategy != TDMAP_BB) return TDMAP_ERR_UNSUPPORTED;
   if (tiled && d > 4) return TDMAP_ERR_UNSUPPORTED;

@@ -60,6 +60,22 @@ struct BatchArgs {
 // One prefix-sum launch plus one persistent launch; ts is 64 or 128.
 hipError_t launch_batched(int ts, const BatchArgs &a);
 
+struct GramArgs {
+  const float *X;      // FP32 points (exact recompute)
+  int64_t N;
+  int d;
+  int64_t ldx;
+  const uint16_t *Xb;  // BF16 points, padded: ceil(N/128)*128 rows of KP features
+  const float *nrm;    // squared norms of the BF16 points
+  int KP;              // features padded to a multiple of 16
+  float *D;            // packed output
+};
+
+// BF16 Gram-form EDM (packed), workspace of gram_workspace_bytes(N, d).
+size_t gram_workspace_bytes(int64_t N, int d);
+hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws,
+                       hipStream_t stream);
+
 // Fill n floats with a value (a kernel, not a memset, so it can sit in a
 // captured graph).
 hipError_t launch_fill(float *p, uint64_t n, float v, hipStream_t stream);
