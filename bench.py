@@ -102,6 +102,102 @@ def cpu_baseline(X: np.ndarray, target_s: float = 10.0):
                       f"({pairs} pairs, {dt:.1f} s, FP64 C loops)"}
 
 
+def _med_ms(fn, reps=10, warmup=2):
+    return float(np.median(time_calls(fn, reps, warmup)))
+
+
+def row_small(torch, tdmap, synth):
+    """1024 points, d = 3, full 1024 x 1024 output, 16 x 16 blocks: LTM vs BB
+    (cache-resident, launch-latency bound) plus g(lambda) for all
+    lambda < 2^16."""
+    N = 1024
+    X = torch.from_numpy(synth.uniform_points(N, 3, seed=synth.workload_seed(1))).cuda()
+    D = torch.empty((N, N), dtype=torch.float32, device="cuda")
+    t_ltm = _med_ms(lambda: tdmap.edm(X, layout="full", strategy="ltm", rho=16, out=D), 200, 10)
+    t_bb = _med_ms(lambda: tdmap.edm(X, layout="full", strategy="bb", rho=16, out=D), 200, 10)
+    ij = torch.empty((1 << 16, 2), dtype=torch.int32, device="cuda")
+    t_map = _med_ms(lambda: tdmap.map_blocks(0, 1 << 16, out=ij), 200, 10)
+    return {"ltm_us": t_ltm * 1e3, "bb_us": t_bb * 1e3, "I": t_bb / t_ltm,
+            "map_blocks_2_16_us": t_map * 1e3,
+            "note": "launch-latency bound (output is cache resident)"}
+
+
+def row_stress(torch, tdmap, synth):
+    """Stress workload: 20000 points, d = 3, packed D, L = sum (D - delta)^2,
+    hand-written backward.  fwd+bwd pairs/s counts the two library kernels;
+    the torch loss ops are reported beside them."""
+    N = 20000
+    X, Xp = synth.stress_inputs(N, 3, seed=synth.workload_seed(4))
+    Xd = torch.from_numpy(X).cuda()
+    delta = tdmap.edm(torch.from_numpy(Xp).cuda(), layout="packed", rho=0)
+    D = torch.empty(N * (N + 1) // 2, dtype=torch.float32, device="cuda")
+    dX = torch.empty((N, 3), dtype=torch.float32, device="cuda")
+    ws = torch.empty(tdmap.tdmap_workspace_size(tdmap.OP_BACKWARD, N, 3, 0, 0, 1),
+                     dtype=torch.uint8, device="cuda")
+    tdmap.edm(Xd, layout="packed", rho=0, out=D)
+    dD = 2.0 * (D - delta)
+    tdmap.edm_backward(Xd, dD, rho=0, deterministic=True, out=dX, workspace=ws)
+    tdmap.edm_backward(Xd, dD, rho=0, deterministic=False, out=dX)
+    torch.cuda.synchronize()
+    pairs = N * (N + 1) // 2
+    t_f = _med_ms(lambda: tdmap.edm(Xd, layout="packed", rho=0, out=D), 20)
+    t_b = _med_ms(lambda: tdmap.edm_backward(Xd, dD, rho=0, deterministic=True, out=dX,
+                                             workspace=ws), 20)
+    t_ba = _med_ms(lambda: tdmap.edm_backward(Xd, dD, rho=0, deterministic=False, out=dX), 20)
+
+    def full_step():
+        tdmap.edm(Xd, layout="packed", rho=0, out=D)
+        r = D - delta
+        _ = (r * r).sum()
+        tdmap.edm_backward(Xd, 2.0 * r, rho=0, deterministic=True, out=dX, workspace=ws)
+    t_step = _med_ms(full_step, 20)
+    bwd_bytes = 4 * pairs
+    return {"N": N, "pairs": pairs, "fwd_us": t_f * 1e3, "bwd_det_us": t_b * 1e3,
+            "bwd_atomic_us": t_ba * 1e3, "fwd_bwd_pairs_per_s": pairs / ((t_f + t_b) * 1e-3),
+            "step_with_torch_loss_us": t_step * 1e3,
+            "fwd_hbm_frac": 4 * pairs / (t_f * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "bwd_hbm_frac": bwd_bytes / (t_b * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "fwd_rho": tdmap.tdmap_tuned_rho(tdmap.OP_EDM, tdmap.LTM, tdmap.PACKED, 3, N),
+            "bwd_rho": tdmap.tdmap_tuned_rho(tdmap.OP_BACKWARD, 0, 0, 3, N)}
+
+
+def row_gram(torch, tdmap, synth):
+    """100000 points, d = 64, BF16 Gram form on MFMA, packed output."""
+    N, d = 100000, 64
+    X, _ = synth.gaussian_with_near_duplicates(N, d, seed=synth.workload_seed(3))
+    Xd = torch.from_numpy(X).cuda()
+    D = torch.empty(N * (N + 1) // 2, dtype=torch.float32, device="cuda")
+    ws = torch.empty(tdmap.tdmap_workspace_size(tdmap.OP_EDM, N, d, 0, 0, tdmap.BF16_GRAM),
+                     dtype=torch.uint8, device="cuda")
+    fn = lambda: tdmap.edm(Xd, layout="packed", rho=0, precision="bf16_gram", out=D,
+                           workspace=ws)
+    t = _med_ms(fn, 10)
+    pairs = N * (N + 1) // 2
+    flops = 2.0 * d * pairs
+    del D
+    return {"N": N, "d": d, "pairs": pairs, "us": t * 1e3, "pairs_per_s": pairs / (t * 1e-3),
+            "hbm_frac": 4 * pairs / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "mfma_frac_bf16": flops / (t * 1e-3) / 2.5e15}
+
+
+def row_batched(torch, tdmap, synth):
+    """4096 sets, n uniform in [64, 4096], d = 3, one persistent launch."""
+    data = synth.batched_sets(4096, 64, 4096, 3, seed=synth.workload_seed(5))
+    Xd = torch.from_numpy(data["X"]).cuda()
+    po = torch.from_numpy(data["point_off"]).cuda()
+    oo = torch.from_numpy(data["out_off"]).cuda()
+    total = int(data["out_off"][-1])
+    D = torch.empty(total, dtype=torch.float32, device="cuda")
+    ws = torch.empty(tdmap.tdmap_workspace_size(tdmap.OP_BATCHED, 0, 3, 4096, 0, 0),
+                     dtype=torch.uint8, device="cuda")
+    fn = lambda: tdmap.edm_batched(Xd, po, oo, rho=0, out=D, workspace=ws)
+    t = _med_ms(fn, 10)
+    del D
+    return {"sets": 4096, "pairs": total, "us": t * 1e3, "pairs_per_s": total / (t * 1e-3),
+            "hbm_frac": 4 * total / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "rho": tdmap.tdmap_tuned_rho(tdmap.OP_BATCHED, 0, 0, 3, 4096)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,7 +262,8 @@ def main():
     wall = time.perf_counter() - t0
     kern_ms = ev0.elapsed_time(ev1) / args.steps
     value = pairs * args.steps / wall
-    log(f"ltm tile {ts_ltm}: {kern_ms * 1e3:.1f} us/step, wall {wall / args.steps * 1e3:.1f} us")
+    log(f"ltm tile {ts_ltm}: {kern_ms * 1e3:.1f} us/step (events), "
+        f"{wall / args.steps * 1e6:.1f} us/step (wall)")
 
     achieved = bytes_alg / (kern_ms * 1e-3) / 1e9
     traffic = stored_traffic()
@@ -212,6 +309,18 @@ def main():
             log(f"rho {rho}: " + ", ".join(f"{s} {row[s]['us']:.0f}us" for s in row))
         comp["paper_style"] = paper
         result["comparison"] = comp
+        del D
+        torch.cuda.empty_cache()
+        rows = {}
+        for name, fn in (("edm_n1024_d3_full", row_small), ("stress_n20000_d3", row_stress),
+                         ("gram_n100000_d64_packed", row_gram),
+                         ("batched_s4096_n64_4096_d3", row_batched)):
+            log(f"row {name} ...")
+            rows[name] = fn(torch, tdmap, synth)
+            torch.cuda.empty_cache()
+            log(f"row {name}: {rows[name]}")
+        result["rows"] = rows
+        result["fwd_bwd_pairs_per_s"] = rows["stress_n20000_d3"]["fwd_bwd_pairs_per_s"]
 
     if not args.skip_cpu:
         log("timing the CPU oracle on a sample ...")
