@@ -91,6 +91,10 @@ int tdmap_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, void *strea
  *   D        device, output in `layout` (pitch ldd for TDMAP_FULL).
  *   strategy one of tdmap_strategy.
  *   rho      the dimensional block size (Sec. II-A):
+ *              1         : (LTM, TDMAP_PACKED, D 16-byte aligned) blocks of
+ *                          one cell: g(lambda) maps every packed position
+ *                          to its cell and the output is written as one
+ *                          linear sweep, four positions per thread;
  *              8, 16, 32 : rho x rho threads per block, one cell per thread,
  *                          as the paper launches every strategy;
  *              64, 128, 256 : (LTM, BB) rho x rho cell tiles per 256-thread
@@ -147,7 +151,10 @@ int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx,
  *   point_off  device, S+1 int64, non-decreasing, point_off[0] = 0.
  *   out_off    device, S+1 int64, out_off[s+1] - out_off[s] =
  *              n_s(n_s+1)/2 with n_s = point_off[s+1] - point_off[s].
- *   rho        tile edge 64 or 128; 0 = autotuned.
+ *   rho        1: one-cell blocks, a persistent linear sweep of the
+ *              concatenated packed output (D_cat 16-byte aligned);
+ *              64 or 128: persistent walk over TS x TS tiles;
+ *              0: autotuned.
  *   workspace  device, tdmap_workspace_size(TDMAP_OP_BATCHED, 0, d, S, rho, 0)
  *              bytes.
  * The offsets are not read on the host (so X_cat and D_cat must be non-NULL

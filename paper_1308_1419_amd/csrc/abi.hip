@@ -254,7 +254,7 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int64
   if (st != TDMAP_OK) return st;
   if (strategy < TDMAP_LTM || strategy > TDMAP_REC) return TDMAP_ERR_INVALID;
   if (precision != TDMAP_FP32 && precision != TDMAP_BF16_GRAM) return TDMAP_ERR_INVALID;
-  if (!(rho == 0 || is_cell_rho(rho) || rho == 64 || rho == 128 || rho == 256))
+  if (!(rho == 0 || rho == 1 || is_cell_rho(rho) || rho == 64 || rho == 128 || rho == 256))
     return TDMAP_ERR_INVALID;
   if (precision == TDMAP_BF16_GRAM) {
     if (strategy != TDMAP_LTM || layout != TDMAP_PACKED || (rho != 0 && rho != 128))
@@ -269,9 +269,12 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int64
   const bool tiled = !is_cell_rho(rho);
   if (tiled && strategy != TDMAP_LTM && strategy != TDMAP_BB) return TDMAP_ERR_UNSUPPORTED;
   if (tiled && d > 4) return TDMAP_ERR_UNSUPPORTED;
+  if (rho == 1 && (strategy != TDMAP_LTM || layout != TDMAP_PACKED ||
+                   (reinterpret_cast<uintptr_t>(D) & 15) != 0))
+    return TDMAP_ERR_UNSUPPORTED;
   if (N == 0) return TDMAP_OK;
   // block index limits: lambda and the UTM thread index are 32-bit
-  const uint64_t edge = tiled ? (rho ? (uint64_t)rho : 64) : (uint64_t)rho;
+  const uint64_t edge = tiled ? (rho > 1 ? (uint64_t)rho : 64) : (uint64_t)rho;
   const uint64_t nb = ceil_div((uint64_t)N, edge);
   if (tri(nb) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
   if (strategy == TDMAP_UTM && tri((uint64_t)N) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
@@ -284,17 +287,23 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int64
     return TDMAP_OK;
   }
   const bool bb = strategy == TDMAP_BB;
+  // rho = 1: the packed linear sweep (g at one-cell granularity)
+  auto run = [&](int c) {
+    return c == 1 ? tdmap::launch_sweep(a) : tdmap::launch_tiled(bb, c, a);
+  };
   int ts = rho;
   if (ts == 0) {
     const TuneKey key(TDMAP_OP_EDM, strategy, layout, d, size_bucket(N));
     ts = tuned_lookup(key);
     if (ts == 0) {
-      ts = autotune({64, 128, 256}, s, [&](int c) { return tdmap::launch_tiled(bb, c, a); }, &st);
+      std::vector<int> cands{64, 128, 256};
+      if (!bb && tdmap::sweep_supported(a)) cands.insert(cands.begin(), 1);
+      ts = autotune(cands, s, run, &st);
       if (st != TDMAP_OK) return st;
       tuned_store(key, ts);
     }
   }
-  TD_HIP(tdmap::launch_tiled(bb, ts, a), "tdmap_edm");
+  TD_HIP(run(ts), "tdmap_edm");
   return TDMAP_OK;
 }
 
@@ -335,28 +344,37 @@ int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets, const int
                       const int64_t *out_off, float *D_cat, int32_t rho, void *workspace,
                       size_t ws_bytes, void *stream) {
   if (num_sets < 0 || d < 1) return TDMAP_ERR_INVALID;
-  if (rho != 0 && rho != 64 && rho != 128) return TDMAP_ERR_INVALID;
+  if (rho != 0 && rho != 1 && rho != 64 && rho != 128) return TDMAP_ERR_INVALID;
   if (num_sets == 0) return TDMAP_OK;
   if (X_cat == nullptr || point_off == nullptr || out_off == nullptr || D_cat == nullptr)
     return TDMAP_ERR_INVALID;
+  const bool aligned = (reinterpret_cast<uintptr_t>(D_cat) & 15) == 0;
+  if (rho == 1 && !aligned) return TDMAP_ERR_UNSUPPORTED;
   if (d > 4) return TDMAP_ERR_UNSUPPORTED;
   const size_t need = tdmap_workspace_size(TDMAP_OP_BATCHED, 0, d, num_sets, rho, 0);
   if (workspace == nullptr || ws_bytes < need) return TDMAP_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   tdmap::BatchArgs a{X_cat, d, num_sets, point_off, out_off, D_cat,
                      reinterpret_cast<uint64_t *>(workspace), s};
+  // rho = 1: persistent linear sweep of the concatenated packed output;
+  // 64 / 128: persistent walk over the prefix-summed tile space
+  auto run = [&](int c) {
+    return c == 1 ? tdmap::launch_batched_sweep(a, 8) : tdmap::launch_batched(c, a);
+  };
   int ts = rho;
   int st = TDMAP_OK;
   if (ts == 0) {
     const TuneKey key(TDMAP_OP_BATCHED, 0, 0, d, size_bucket(num_sets));
     ts = tuned_lookup(key);
     if (ts == 0) {
-      ts = autotune({64, 128}, s, [&](int c) { return tdmap::launch_batched(c, a); }, &st);
+      std::vector<int> cands{64, 128};
+      if (aligned) cands.insert(cands.begin(), 1);
+      ts = autotune(cands, s, run, &st);
       if (st != TDMAP_OK) return st;
       tuned_store(key, ts);
     }
   }
-  TD_HIP(tdmap::launch_batched(ts, a), "tdmap_edm_batched");
+  TD_HIP(run(ts), "tdmap_edm_batched");
   return TDMAP_OK;
 }
 

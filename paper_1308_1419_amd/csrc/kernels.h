@@ -76,6 +76,12 @@ size_t gram_workspace_bytes(int64_t N, int d);
 hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws,
                        hipStream_t stream);
 
+// Packed layout written as a linear sweep (g at one-cell granularity).
+bool sweep_supported(const EdmArgs &a);
+hipError_t launch_sweep(const EdmArgs &a);
+// Batched packed sweep with a persistent grid of wgs_per_cu work-groups per CU.
+hipError_t launch_batched_sweep(const BatchArgs &a, int wgs_per_cu);
+
 // Fill n floats with a value (a kernel, not a memset, so it can sit in a
 // captured graph).
 hipError_t launch_fill(float *p, uint64_t n, float v, hipStream_t stream);

@@ -1,0 +1,215 @@
+// Packed-layout EDM as a linear sweep of the output.
+//
+// In the packed layout the index of cell (i, j) is i(i+1)/2 + j, which is
+// exactly the block index lambda of Sec. II-A, Eq. (1) for blocks of one
+// cell.  So g(lambda) with rho = 1 maps every output position back to its
+// cell, and the output can be written in address order: each thread owns
+// four consecutive positions (one aligned 16-byte store) and each
+// work-group 1024 consecutive positions.  The map runs once per wave (a
+// wave's 256 positions span at most a couple of rows); each lane then
+// steps from the wave's first cell to its own.
+//
+// The batched variant sweeps the concatenation of every set's packed
+// triangle; positions past the end of a set continue in the next one.
+#include "device.h"
+#include "kernels.h"
+
+namespace tdmap {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// g(lambda) for 64-bit lambda (packed indices pass 2^32 at N = 92682).  The
+// single-precision guess of the row is within one for lambda < 2^40; the
+// bounded loops make the result exact.
+__device__ __forceinline__ void g_lambda64(uint64_t lam, uint64_t &i, uint64_t &j) {
+  const float x = __builtin_fmaf(2.0f, (float)lam, 0.25f);
+  const float s = x * __builtin_amdgcn_rsqf(x);
+  uint64_t r = (uint64_t)__builtin_fmaxf(s - 0.5f, 0.0f);
+  uint64_t t = tri64(r);
+  while (t > lam) {
+    --r;
+    t -= r + 1;
+  }
+  while (t + r + 1 <= lam) {
+    t += r + 1;
+    ++r;
+  }
+  i = r;
+  j = lam - t;
+}
+
+template <int D>
+__device__ __forceinline__ void load_pt(const float *__restrict__ X, int64_t ldx, uint64_t p,
+                                        float (&v)[D]) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) v[k] = X[p * ldx + k];
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void edm_sweep_kernel(const float *__restrict__ X, int64_t N,
+                                                        int64_t ldx, float *__restrict__ out,
+                                                        uint64_t total, uint64_t e_base) {
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t ew = e_base + (uint64_t)blockIdx.x * 1024 + (uint64_t)w * 256;
+  if (ew >= total) return;
+  uint64_t iw, jw;
+  g_lambda64(ew, iw, jw);
+  const uint32_t l = threadIdx.x & 63;
+  const uint64_t e0 = ew + 4 * l;
+  if (e0 >= total) return;
+  uint64_t i = iw, j = jw + 4 * l;
+  while (j > i) {
+    j -= i + 1;
+    ++i;
+  }
+  float xi[D];
+  load_pt<D>(X, ldx, i, xi);
+  float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (e0 + q >= total) break;
+    if (j > i) {  // next row
+      ++i;
+      j = 0;
+      load_pt<D>(X, ldx, i, xi);
+    }
+    float xj[D];
+    load_pt<D>(X, ldx, j, xj);
+    v[q] = pair_dist<D>(xi, xj);
+    ++j;
+  }
+  if (e0 + 4 <= total) {
+    f4 o = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(o, reinterpret_cast<f4 *>(out + e0));
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (e0 + q < total) __builtin_nontemporal_store(v[q], out + e0 + q);
+  }
+}
+
+// Batched: positions [0, out_off[S]) of the concatenated packed triangles,
+// swept by a persistent grid.  Work-group b owns a contiguous run of
+// 1024-position pieces; the set of a position comes from out_off (one
+// binary search per wave, then forward steps), so nothing is read on the
+// host.
+template <int D>
+__global__ __launch_bounds__(256) void edm_batched_sweep_kernel(BatchArgs a) {
+  const int64_t *__restrict__ oo = a.out_off;
+  const uint64_t total = (uint64_t)oo[a.num_sets];
+  const uint64_t pieces = (total + 1023) / 1024;
+  const uint64_t per = (pieces + gridDim.x - 1) / gridDim.x;
+  const uint64_t p_lo = (uint64_t)blockIdx.x * per;
+  const uint64_t p_hi = p_lo + per < pieces ? p_lo + per : pieces;
+  if (p_lo >= p_hi) return;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t l = threadIdx.x & 63;
+  // set of the wave's first position
+  const uint64_t e_first = p_lo * 1024 + (uint64_t)w * 256;
+  int32_t s0 = 0, s1 = a.num_sets;
+  while (s1 - s0 > 1) {
+    const int32_t mid = (s0 + s1) >> 1;
+    if ((uint64_t)oo[mid] <= e_first) s0 = mid; else s1 = mid;
+  }
+  int32_t sw = s0;
+  float *__restrict__ out = a.D;
+  for (uint64_t p = p_lo; p < p_hi; ++p) {
+    const uint64_t ew = p * 1024 + (uint64_t)w * 256;
+    if (ew >= total) break;
+    while ((uint64_t)oo[sw + 1] <= ew) ++sw;
+    const uint64_t e0 = ew + 4 * l;
+    if (e0 >= total) continue;
+    int32_t s = sw;
+    while ((uint64_t)oo[s + 1] <= e0) ++s;
+    uint64_t i, j;
+    g_lambda64(e0 - (uint64_t)oo[s], i, j);
+    int64_t n = a.point_off[s + 1] - a.point_off[s];
+    const float *__restrict__ Xs = a.X + a.point_off[s] * D;
+    float xi[D];
+    load_pt<D>(Xs, D, i, xi);
+    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (e0 + q >= total) break;
+      if (j > i) {
+        ++i;
+        j = 0;
+        if ((int64_t)i >= n) {  // first row of the next non-empty set
+          do {
+            ++s;
+          } while ((uint64_t)oo[s + 1] <= e0 + q);
+          i = 0;
+          n = a.point_off[s + 1] - a.point_off[s];
+          Xs = a.X + a.point_off[s] * D;
+        }
+        load_pt<D>(Xs, D, i, xi);
+      }
+      float xj[D];
+      load_pt<D>(Xs, D, j, xj);
+      v[q] = pair_dist<D>(xi, xj);
+      ++j;
+    }
+    if (e0 + 4 <= total) {
+      f4 o = {v[0], v[1], v[2], v[3]};
+      __builtin_nontemporal_store(o, reinterpret_cast<f4 *>(out + e0));
+    } else {
+      for (int q = 0; q < 4; ++q)
+        if (e0 + q < total) __builtin_nontemporal_store(v[q], out + e0 + q);
+    }
+  }
+}
+
+template <int D>
+static hipError_t launch_sweep_t(const EdmArgs &a) {
+  const uint64_t total = (uint64_t)a.N * (uint64_t)(a.N + 1) / 2;
+  const uint64_t per_launch = (uint64_t)1024 * (((uint64_t)1 << 31) / 256);
+  for (uint64_t b = 0; b < total; b += per_launch) {
+    const uint64_t c = total - b < per_launch ? total - b : per_launch;
+    hipLaunchKernelGGL(edm_sweep_kernel<D>, dim3((uint32_t)((c + 1023) / 1024)), dim3(256), 0,
+                       a.stream, a.X, a.N, a.ldx, a.D, b + c, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+bool sweep_supported(const EdmArgs &a) {
+  return a.layout == kLayoutPacked && a.d >= 1 && a.d <= 4 &&
+         (reinterpret_cast<uintptr_t>(a.D) & 15) == 0;
+}
+
+hipError_t launch_sweep(const EdmArgs &a) {
+  if (a.N == 0) return hipSuccess;
+  switch (a.d) {
+    case 1: return launch_sweep_t<1>(a);
+    case 2: return launch_sweep_t<2>(a);
+    case 3: return launch_sweep_t<3>(a);
+    case 4: return launch_sweep_t<4>(a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static int g_sweep_cus = 0;
+
+hipError_t launch_batched_sweep(const BatchArgs &a, int wgs_per_cu) {
+  if (a.num_sets == 0) return hipSuccess;
+  if (g_sweep_cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      g_sweep_cus = n;
+    else
+      g_sweep_cus = 256;
+  }
+  const dim3 grid((uint32_t)(g_sweep_cus * wgs_per_cu));
+  switch (a.d) {
+    case 1: hipLaunchKernelGGL(edm_batched_sweep_kernel<1>, grid, dim3(256), 0, a.stream, a); break;
+    case 2: hipLaunchKernelGGL(edm_batched_sweep_kernel<2>, grid, dim3(256), 0, a.stream, a); break;
+    case 3: hipLaunchKernelGGL(edm_batched_sweep_kernel<3>, grid, dim3(256), 0, a.stream, a); break;
+    case 4: hipLaunchKernelGGL(edm_batched_sweep_kernel<4>, grid, dim3(256), 0, a.stream, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace tdmap

@@ -54,7 +54,7 @@ def _run(sizes, d, rho, seed, guard=256):
     return X, point_off, out_off, buf
 
 
-@pytest.mark.parametrize("rho", [64, 128, 0])
+@pytest.mark.parametrize("rho", [1, 64, 128, 0])
 @pytest.mark.parametrize("d", [1, 3, 4])
 def test_batched_ragged_sets(rho, d):
     _require_gpu()
@@ -84,14 +84,18 @@ def test_batched_empty_and_single():
     tdmap.tdmap_edm_batched(0, 3, 0, 0, 0, 0, 64, 0, 0, 0)
 
 
-def test_batched_many_small_sets():
+@pytest.mark.parametrize("rho", [1, 64, 0])
+def test_batched_many_small_sets(rho):
+    # sizes 0..139: the sweep crosses many set boundaries inside one thread
     _require_gpu()
     rng = np.random.default_rng(9)
-    sizes = rng.integers(1, 140, size=3000)
-    X, po, oo, buf = _run(sizes, 3, 0, seed=3)
+    sizes = rng.integers(0, 140, size=3000)
+    sizes[:40] = [0, 1, 2, 1, 0, 0, 3, 1, 1, 2] * 4
+    X, po, oo, buf = _run(sizes, 3, rho, seed=3)
     got = buf.cpu().numpy()
     ref = oedm.edm64_batched(X, po)
-    _check_rel(got[: len(ref)], ref, "3000 small sets")
+    _check_rel(got[: len(ref)], ref, f"3000 small sets rho={rho}")
+    assert np.all(got.view(np.int32)[len(ref):] == SENTINEL)
 
 
 def test_batched_workload_full_size():
@@ -105,9 +109,16 @@ def test_batched_workload_full_size():
     buf = torch.empty(total + 1024, dtype=torch.float32, device="cuda")
     buf.view(torch.int32).fill_(SENTINEL)
     Xd = torch.from_numpy(X).cuda()
-    tdmap.edm_batched(Xd, torch.from_numpy(po).cuda(), torch.from_numpy(oo).cuda(), rho=0,
-                      out=buf[:total])
+    pod, ood = torch.from_numpy(po).cuda(), torch.from_numpy(oo).cuda()
+    tdmap.edm_batched(Xd, pod, ood, rho=0, out=buf[:total])
     torch.cuda.synchronize()
+    # the two persistent walks (linear sweep, tiles) write identical bits
+    other = torch.empty(total, dtype=torch.float32, device="cuda")
+    chosen = tdmap.tdmap_tuned_rho(tdmap.OP_BATCHED, 0, 0, 3, 4096)
+    tdmap.edm_batched(Xd, pod, ood, rho=64 if chosen == 1 else 1, out=other)
+    torch.cuda.synchronize()
+    assert torch.equal(other.view(torch.int32), buf[:total].view(torch.int32))
+    del other
     bits = buf.view(torch.int32)
     assert not bool(torch.any(bits[:total] == SENTINEL)), "a cell was not written"
     assert bool(torch.all(bits[total:] == SENTINEL)), "wrote past the last set"

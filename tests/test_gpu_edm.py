@@ -224,6 +224,25 @@ def test_edm_tiled_packed_and_unaligned(strategy, rho, d):
     _check_full(F, X, ld=N + 1)
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 31, 64, 1000, 1037, 2900])
+def test_edm_packed_sweep(N, d):
+    # rho = 1: one-cell blocks, the packed output written as a linear sweep
+    _require_gpu()
+    X = synth.uniform_points(N, d, seed=400 + N + d)
+    Xd = torch.from_numpy(X).cuda()
+    guard = 64
+    buf = torch.empty(N * (N + 1) // 2 + guard, dtype=torch.float32, device="cuda")
+    buf.view(torch.int32).fill_(int(SENTINEL))
+    D = buf[: N * (N + 1) // 2]
+    tdmap.edm(Xd, layout="packed", strategy="ltm", rho=1, out=D)
+    torch.cuda.synchronize()
+    _check_rel(D.cpu().numpy(), oedm.edm64_packed(X), f"sweep N={N} d={d}")
+    assert np.all(buf[-guard:].cpu().numpy().view(np.int32) == SENTINEL), "wrote past the end"
+    R = tdmap.edm(Xd, layout="packed", strategy="ltm", rho=16)
+    assert torch.equal(D.view(torch.int32), R.view(torch.int32))
+
+
 def test_edm_autotuned_matches():
     _require_gpu()
     tdmap.tdmap_autotune_reset()
