@@ -206,6 +206,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--only-main", action="store_true",
                     help="time only the main step (for profiler runs)")
+    ap.add_argument("--row", default=None,
+                    help="run only one named workload row (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy three times (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -218,6 +220,14 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copied 3 x 2^30 bytes")
+        return
+    if args.row:
+        import torch
+        from paper_1308_1419_amd import synth, tdmap
+        fn = {"edm_n1024_d3_full": row_small, "stress_n20000_d3": row_stress,
+              "gram_n100000_d64_packed": row_gram,
+              "batched_s4096_n64_4096_d3": row_batched}[args.row]
+        print(json.dumps({args.row: fn(torch, tdmap, synth)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "

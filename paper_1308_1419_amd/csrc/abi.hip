@@ -367,9 +367,9 @@ int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets, const int
     const TuneKey key(TDMAP_OP_BATCHED, 0, 0, d, size_bucket(num_sets));
     ts = tuned_lookup(key);
     if (ts == 0) {
-      std::vector<int> cands{64, 128};
-      if (aligned) cands.insert(cands.begin(), 1);
-      ts = autotune(cands, s, run, &st);
+      // the linear sweep (rho = 1) re-reads each set's points for every row
+      // it touches and loses to the tile walks; it is only run on request
+      ts = autotune({64, 128}, s, run, &st);
       if (st != TDMAP_OK) return st;
       tuned_store(key, ts);
     }

@@ -62,43 +62,93 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
   __syncthreads();
 
   const bool diag = I == J;
-  for (int rr = 0; rr < RPW; ++rr) {
-    const int r = rr * 4 + w;
-    const int64_t i = row0 + r;
-    float rs[D];
+  const bool interior = (J < I) && (row0 + TS <= N);
+  if (interior) {
+    // every cell of the tile is a live j < i cell: the dD loads are
+    // unconditional and issued four rows at a time
+    constexpr int RB = 4;
+    for (int rb = 0; rb < RPW; rb += RB) {
+      float g[RB][CPL];
 #pragma unroll
-    for (int k = 0; k < D; ++k) rs[k] = 0.0f;
-    if (i < N) {
-      float xi[D];
+      for (int q = 0; q < RB; ++q) {
+        const int64_t i = row0 + (rb + q) * 4 + w;
+        const uint64_t base = out_index<LAYOUT>((uint64_t)i, (uint64_t)col0, a.ldd);
 #pragma unroll
-      for (int k = 0; k < D; ++k) xi[k] = xs[r * D + k];
-      const uint64_t base = out_index<LAYOUT>((uint64_t)i, (uint64_t)col0, a.ldd);
+        for (int c = 0; c < CPL; ++c) g[q][c] = a.dD[base + l + 64 * c];
+      }
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int64_t j = col0 + l + 64 * c;
-        const bool ok = jok[c] && (!diag || j < i);
-        const float g = ok ? a.dD[base + l + 64 * c] : 0.0f;
-        float diff[D];
-        float s = 0.0f;
+      for (int q = 0; q < RB; ++q) {
+        const int r = (rb + q) * 4 + w;
+        float xi[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-          diff[k] = xi[k] - xj[c][k];
-          s = __builtin_fmaf(diff[k], diff[k], s);
+        for (int k = 0; k < D; ++k) xi[k] = xs[r * D + k];
+        float rs[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) rs[k] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          float diff[D];
+          float s2 = 0.0f;
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            diff[k] = xi[k] - xj[c][k];
+            s2 = __builtin_fmaf(diff[k], diff[k], s2);
+          }
+          const float cc = s2 > 0.0f ? g[q][c] * __builtin_amdgcn_rsqf(s2) : 0.0f;
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            const float v = cc * diff[k];
+            rs[k] += v;
+            cacc[c][k] -= v;
+          }
         }
-        const float cc = (ok && s > 0.0f) ? g * __builtin_amdgcn_rsqf(s) : 0.0f;
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-          const float v = cc * diff[k];
-          rs[k] += v;
-          cacc[c][k] -= v;
+        for (int k = 0; k < D; ++k) rs[k] = wave_sum(rs[k]);
+        if (l == 0) {
+#pragma unroll
+          for (int k = 0; k < D; ++k) rowp[r * D + k] = rs[k];
         }
       }
     }
+  } else {
+    for (int rr = 0; rr < RPW; ++rr) {
+      const int r = rr * 4 + w;
+      const int64_t i = row0 + r;
+      float rs[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) rs[k] = wave_sum(rs[k]);
-    if (l == 0) {
+      for (int k = 0; k < D; ++k) rs[k] = 0.0f;
+      if (i < N) {
+        float xi[D];
 #pragma unroll
-      for (int k = 0; k < D; ++k) rowp[r * D + k] = rs[k];
+        for (int k = 0; k < D; ++k) xi[k] = xs[r * D + k];
+        const uint64_t base = out_index<LAYOUT>((uint64_t)i, (uint64_t)col0, a.ldd);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          const int64_t j = col0 + l + 64 * c;
+          const bool ok = jok[c] && (!diag || j < i);
+          const float g = ok ? a.dD[base + l + 64 * c] : 0.0f;
+          float diff[D];
+          float s2 = 0.0f;
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            diff[k] = xi[k] - xj[c][k];
+            s2 = __builtin_fmaf(diff[k], diff[k], s2);
+          }
+          const float cc = (ok && s2 > 0.0f) ? g * __builtin_amdgcn_rsqf(s2) : 0.0f;
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            const float v = cc * diff[k];
+            rs[k] += v;
+            cacc[c][k] -= v;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) rs[k] = wave_sum(rs[k]);
+      if (l == 0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) rowp[r * D + k] = rs[k];
+      }
     }
   }
 #pragma unroll

@@ -57,12 +57,42 @@ __global__ __launch_bounds__(1024) void batched_prefix_kernel(const int64_t *__r
   }
 }
 
+// Everything a tile needs to know about its set and position.
+struct TileRef {
+  int32_t s;
+  uint32_t I, J;
+  int64_t n;
+  int64_t p0;
+  int64_t o0;
+};
+
+__device__ __forceinline__ TileRef locate_tile(const uint64_t *__restrict__ P,
+                                               const int64_t *__restrict__ point_off,
+                                               const int64_t *__restrict__ out_off, int32_t s,
+                                               uint64_t g) {
+  while (P[s + 1] <= g) ++s;
+  TileRef t;
+  t.s = s;
+  g_lambda((uint32_t)(g - P[s]), t.I, t.J);
+  t.p0 = point_off[s];
+  t.n = point_off[s + 1] - t.p0;
+  t.o0 = out_off[s];
+  return t;
+}
+
+// The kernel arguments are separate restrict pointers, so the uniform row
+// point loads go through the scalar cache (their wait counter does not
+// include the vector stores), and the next tile's column points are loaded
+// before the current tile's stores are issued.
 template <int TS, int D>
-__global__ __launch_bounds__(256) void edm_batched_kernel(BatchArgs a) {
+__global__ __launch_bounds__(256) void edm_batched_kernel(const float *__restrict__ X,
+                                                          const int64_t *__restrict__ point_off,
+                                                          const int64_t *__restrict__ out_off,
+                                                          const uint64_t *__restrict__ P,
+                                                          int32_t num_sets, float *__restrict__ Dout) {
   constexpr int CPL = TS / 64;
   constexpr int RPW = TS / 4;
-  const uint64_t *__restrict__ P = a.blk_off;
-  const uint64_t total = P[a.num_sets];
+  const uint64_t total = P[num_sets];
   const uint64_t G = gridDim.x;
   const uint64_t chunk = (total + G - 1) / G;
   const uint64_t lo = (uint64_t)blockIdx.x * chunk;
@@ -70,34 +100,41 @@ __global__ __launch_bounds__(256) void edm_batched_kernel(BatchArgs a) {
   if (lo >= hi) return;
 
   // largest s with P[s] <= lo (P is non-decreasing, P[0] = 0)
-  int32_t s0 = 0, s1 = a.num_sets;
+  int32_t s0 = 0, s1 = num_sets;
   while (s1 - s0 > 1) {
     const int32_t mid = (s0 + s1) >> 1;
     if (P[mid] <= lo) s0 = mid; else s1 = mid;
   }
-  int32_t s = s0;
 
   const int l = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  TileRef cur = locate_tile(P, point_off, out_off, s0, lo);
+  float xj[CPL][D];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    const int64_t j = (int64_t)cur.J * TS + l + 64 * c;
+#pragma unroll
+    for (int k = 0; k < D; ++k) xj[c][k] = j < cur.n ? X[(cur.p0 + j) * D + k] : 0.0f;
+  }
   for (uint64_t g = lo; g < hi; ++g) {
-    while (P[s + 1] <= g) ++s;
-    uint32_t I, J;
-    g_lambda((uint32_t)(g - P[s]), I, J);
-    const int64_t p0 = a.point_off[s];
-    const int64_t n = a.point_off[s + 1] - p0;
-    const float *__restrict__ Xs = a.X + p0 * D;
-    float *__restrict__ out = a.D + a.out_off[s];
-    const int64_t row0 = (int64_t)I * TS;
-    const int64_t col0 = (int64_t)J * TS;
-
-    float xj[CPL][D];
+    // prefetch the next tile's column points before this tile's stores
+    TileRef nxt = cur;
+    float xn[CPL][D];
+    if (g + 1 < hi) {
+      nxt = locate_tile(P, point_off, out_off, cur.s, g + 1);
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      const int64_t j = col0 + l + 64 * c;
+      for (int c = 0; c < CPL; ++c) {
+        const int64_t j = (int64_t)nxt.J * TS + l + 64 * c;
 #pragma unroll
-      for (int k = 0; k < D; ++k) xj[c][k] = j < n ? Xs[j * D + k] : 0.0f;
+        for (int k = 0; k < D; ++k) xn[c][k] = j < nxt.n ? X[(nxt.p0 + j) * D + k] : 0.0f;
+      }
     }
-    const bool interior = (J < I) && (row0 + TS <= n);
+    const float *__restrict__ Xs = X + cur.p0 * D;
+    float *__restrict__ out = Dout + cur.o0;
+    const int64_t n = cur.n;
+    const int64_t row0 = (int64_t)cur.I * TS;
+    const int64_t col0 = (int64_t)cur.J * TS;
+    const bool interior = (cur.J < cur.I) && (row0 + TS <= n);
     if (interior) {
 #pragma unroll 4
       for (int rr = 0; rr < RPW; ++rr) {
@@ -124,6 +161,11 @@ __global__ __launch_bounds__(256) void edm_batched_kernel(BatchArgs a) {
         }
       }
     }
+    cur = nxt;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+#pragma unroll
+      for (int k = 0; k < D; ++k) xj[c][k] = xn[c][k];
   }
 }
 
@@ -153,7 +195,8 @@ static hipError_t launch_batched_t(const BatchArgs &a) {
       per_cu <= 0)
     per_cu = 4;
   const uint32_t grid = (uint32_t)(cu_count() * per_cu);
-  hipLaunchKernelGGL((edm_batched_kernel<TS, D>), dim3(grid), dim3(256), 0, a.stream, a);
+  hipLaunchKernelGGL((edm_batched_kernel<TS, D>), dim3(grid), dim3(256), 0, a.stream, a.X,
+                     a.point_off, a.out_off, a.blk_off, a.num_sets, a.D);
   return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void gram_prologue_kernel(const float *__restr
 // FP32 difference form with eight interleaved partial sums combined as a
 // tree, which keeps the rounding error of the squared distance near
 // (d/8 + 6) units of roundoff.
-__device__ __noinline__ float exact_dist(const float *__restrict__ X, int64_t ldx, int d, int64_t i,
+__device__ __forceinline__ float exact_dist(const float *__restrict__ X, int64_t ldx, int d, int64_t i,
                                          int64_t j) {
   float s[8];
 #pragma unroll
@@ -74,6 +74,49 @@ __device__ __noinline__ float exact_dist(const float *__restrict__ X, int64_t ld
   return __builtin_amdgcn_sqrtf(q);
 }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Writes the 128 x 128 tile held in LDS to the packed output.  Each wave
+// owns 32 tile rows and writes two per instruction (one per half-wave).
+// Packed row i's segment [col0, col0 + 128) starts sh = (i(i+1)/2 + col0)
+// mod 4 positions past a 16-byte boundary; half-wave lane h stores the
+// aligned chunk at columns col0 - sh + 4h .. + 3, read back from LDS at that
+// shift.  Lane 0 of each half-wave writes the 4 - sh head cells and the sh
+// tail cells one by one (the neighbouring tiles write the rest of those two
+// chunks).  Diagonal and edge rows go cell by cell.
+__device__ __forceinline__ void store_tile_rows(const float (*tileD)[kGramTile + 4], int64_t row0,
+                                                int64_t col0, int64_t N, bool diag,
+                                                float *__restrict__ out) {
+  const int w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63;
+  const int h = l & 31;
+  const bool full_rows = !diag && row0 + kGramTile <= N;
+  for (int p = 0; p < 16; ++p) {
+    const int r = w * 32 + 2 * p + (l >> 5);
+    const int64_t i = row0 + r;
+    if (i >= N) continue;
+    const uint64_t first = tri64((uint64_t)i) + (uint64_t)col0;
+    if (full_rows) {
+      const int sh = (int)(first & 3);
+      const uint64_t A0 = first - (uint64_t)sh;
+      if (h > 0 || sh == 0) {
+        const int c = 4 * h - sh;
+        f4 v = {tileD[r][c], tileD[r][c + 1], tileD[r][c + 2], tileD[r][c + 3]};
+        __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(out + A0 + 4 * h));
+      } else {
+        for (int q = sh; q < 4; ++q) __builtin_nontemporal_store(tileD[r][q - sh], out + A0 + q);
+        for (int q = 0; q < sh; ++q)
+          __builtin_nontemporal_store(tileD[r][kGramTile - sh + q], out + A0 + kGramTile + q);
+      }
+    } else {
+      // last valid column of this row inside the tile
+      const int64_t jmax = (diag ? i : N - 1) - col0;
+      for (int c = h; c < kGramTile; c += 32)
+        if (c <= jmax) __builtin_nontemporal_store(tileD[r][c], out + first + c);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void gram_tile_kernel(GramArgs a, uint32_t lam0) {
   uint32_t I, J;
   g_lambda(lam0 + blockIdx.x, I, J);
@@ -82,12 +125,13 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(GramArgs a, uint32_t lam
   const int l = t & 63;
   const int wr = w >> 1;
   const int wc = w & 1;
-  // the upper-right quadrant of a diagonal tile lies above the diagonal
-  if (I == J && wr < wc) return;
   const int64_t r0 = (int64_t)I * kGramTile + wr * 64;
   const int64_t c0 = (int64_t)J * kGramTile + wc * 64;
   const int KP = a.KP;
   const uint16_t *__restrict__ Xb = a.Xb;
+  // the upper-right quadrant of a diagonal tile lies above the diagonal:
+  // its wave skips the products but still stores its share of the rows
+  const bool above = I == J && wr < wc;
 
   f32x16 acc[2][2];
 #pragma unroll
@@ -102,7 +146,7 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(GramArgs a, uint32_t lam
   // assignment for its points, so the product is x_i . x_j.
   const int lr = l & 31;
   const int lk = (l >> 5) * 8;
-  for (int k = 0; k < KP; k += 16) {
+  for (int k = 0; k < (above ? 0 : KP); k += 16) {
     bf16x8 av[2], bv[2];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
@@ -117,31 +161,53 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(GramArgs a, uint32_t lam
   }
 
   // accumulator v of a 32 x 32 block holds row (v/4)*8 + (l/32)*4 + v%4 and
-  // column l % 32
+  // column l % 32.  The norms of every row and column this lane touches are
+  // loaded up front (the padded norm array covers every tile row).
   const int64_t N = a.N;
-  float *__restrict__ out = a.D;
+  float nr[2][16];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+      nr[bi][v] = a.nrm[r0 + bi * 32 + (v >> 2) * 8 + (l >> 5) * 4 + (v & 3)];
+  float nc[2];
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj) nc[bj] = a.nrm[c0 + bj * 32 + lr];
+
+  // distances go to an LDS copy of the tile first: sqrt(G) for every pair
+  // above the recompute threshold, then (rare: the diagonal and
+  // near-duplicate pairs) the exact FP32 difference form for the others
+  __shared__ float tileD[kGramTile][kGramTile + 4];
+  const int tr0 = wr * 64;
+  const int tc0 = wc * 64;
+  uint64_t need = 0;
 #pragma unroll
   for (int bj = 0; bj < 2; ++bj) {
-    const int64_t j = c0 + bj * 32 + lr;
-    const float nj = a.nrm[j];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t i = r0 + bi * 32 + (v >> 2) * 8 + (l >> 5) * 4 + (v & 3);
-        if (i < N && j <= i) {
-          const float sn = a.nrm[i] + nj;
-          const float G = __builtin_fmaf(-2.0f, acc[bi][bj][v], sn);
-          float dv;
-          if (G <= kGramTheta * sn)
-            dv = exact_dist(a.X, a.ldx, a.d, i, j);
-          else
-            dv = __builtin_amdgcn_sqrtf(G);
-          __builtin_nontemporal_store(dv, out + tri64((uint64_t)i) + j);
-        }
+      for (int v = 0; v < 16 && !above; ++v) {
+        const int rr = bi * 32 + (v >> 2) * 8 + (l >> 5) * 4 + (v & 3);
+        const float sn = nr[bi][v] + nc[bj];
+        const float G = __builtin_fmaf(-2.0f, acc[bi][bj][v], sn);
+        if (G <= kGramTheta * sn) need |= (uint64_t)1 << ((bj * 2 + bi) * 16 + v);
+        tileD[tr0 + rr][tc0 + bj * 32 + lr] = __builtin_amdgcn_sqrtf(__builtin_fmaxf(G, 0.0f));
       }
     }
   }
+  while (need) {
+    const int b = __builtin_ctzll(need);
+    need &= need - 1;
+    const int bj = b >> 5;
+    const int bi = (b >> 4) & 1;
+    const int v = b & 15;
+    const int rr = bi * 32 + (v >> 2) * 8 + (l >> 5) * 4 + (v & 3);
+    const int64_t i = r0 + rr;
+    const int64_t j = c0 + bj * 32 + lr;
+    if (i < N && j <= i) tileD[tr0 + rr][tc0 + bj * 32 + lr] = exact_dist(a.X, a.ldx, a.d, i, j);
+  }
+  __syncthreads();
+  store_tile_rows(tileD, (int64_t)I * kGramTile, (int64_t)J * kGramTile, N, I == J, a.D);
 }
 
 size_t gram_workspace_bytes(int64_t N, int d) {

@@ -24,6 +24,90 @@ namespace tdmap {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+// Interior tile rows in the packed layout with 16-byte stores (TS = 256:
+// one row per wave and pass).  Packed row i starts at i(i+1)/2, so the
+// tile's row segment [col0, col0 + 256) begins s = (i(i+1)/2 + col0) mod 4
+// positions past a 16-byte boundary.  Lane l stores the aligned chunk
+// holding columns col0 - s + 4l .. col0 - s + 4l + 3; for lanes 1..63 those
+// all lie in the segment, so each of them needs the points of columns
+// col0 + 4l - 3 .. col0 + 4l + 3 (kept in registers) and picks four of them
+// by s, which is uniform across the wave.  Lane 0 writes the 4 - s head
+// cells and the s tail cells (col0 + 256 - s .. col0 + 255) one by one; the
+// neighbouring tiles write the rest of the two shared chunks.
+template <int TS, int D>
+__device__ __forceinline__ void packed_vec_rows(const EdmArgs &a, const float *xs, int64_t row0,
+                                                int64_t col0, int lr, float *__restrict__ out) {
+  static_assert(TS == 256, "one tile row per wave");
+  const int l = threadIdx.x & 63;
+  float win[7][D];
+#pragma unroll
+  for (int o = 0; o < 7; ++o) {
+    const int64_t c = col0 + 4 * l - 3 + o;
+#pragma unroll
+    for (int k = 0; k < D; ++k) win[o][k] = c >= 0 ? a.X[c * a.ldx + k] : 0.0f;
+  }
+  float tail[3][D];
+#pragma unroll
+  for (int o = 0; o < 3; ++o)
+#pragma unroll
+    for (int k = 0; k < D; ++k) tail[o][k] = a.X[(col0 + 253 + o) * a.ldx + k];
+  constexpr int PASSES = TS / 4;
+#pragma unroll 4
+  for (int ps = 0; ps < PASSES; ++ps) {
+    const int r = lr + ps * 4;
+    const uint64_t i = (uint64_t)(row0 + r);
+    float xi[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xi[k] = xs[r * D + k];
+    const uint64_t first = tri64(i) + (uint64_t)col0;
+    const int sh = (int)(first & 3);
+    const uint64_t A0 = first - (uint64_t)sh;
+    float v0, v1, v2, v3;
+    switch (sh) {
+      case 0:
+        v0 = pair_dist<D>(xi, win[3]); v1 = pair_dist<D>(xi, win[4]);
+        v2 = pair_dist<D>(xi, win[5]); v3 = pair_dist<D>(xi, win[6]);
+        break;
+      case 1:
+        v0 = pair_dist<D>(xi, win[2]); v1 = pair_dist<D>(xi, win[3]);
+        v2 = pair_dist<D>(xi, win[4]); v3 = pair_dist<D>(xi, win[5]);
+        break;
+      case 2:
+        v0 = pair_dist<D>(xi, win[1]); v1 = pair_dist<D>(xi, win[2]);
+        v2 = pair_dist<D>(xi, win[3]); v3 = pair_dist<D>(xi, win[4]);
+        break;
+      default:
+        v0 = pair_dist<D>(xi, win[0]); v1 = pair_dist<D>(xi, win[1]);
+        v2 = pair_dist<D>(xi, win[2]); v3 = pair_dist<D>(xi, win[3]);
+        break;
+    }
+    if (l > 0 || sh == 0) {
+      f4 v = {v0, v1, v2, v3};
+      __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(out + A0 + 4 * l));
+    } else {
+      // head: chunk positions sh..3 hold columns col0 .. col0 + 3 - sh
+      if (sh <= 1) __builtin_nontemporal_store(v1, out + A0 + 1);
+      if (sh <= 2) __builtin_nontemporal_store(v2, out + A0 + 2);
+      __builtin_nontemporal_store(v3, out + A0 + 3);
+      // tail: columns col0 + 256 - sh .. col0 + 255 (tail[o] is column
+      // col0 + 253 + o)
+      const float t0 = pair_dist<D>(xi, tail[0]);
+      const float t1 = pair_dist<D>(xi, tail[1]);
+      const float t2 = pair_dist<D>(xi, tail[2]);
+      if (sh == 1) {
+        __builtin_nontemporal_store(t2, out + A0 + 256);
+      } else if (sh == 2) {
+        __builtin_nontemporal_store(t1, out + A0 + 256);
+        __builtin_nontemporal_store(t2, out + A0 + 257);
+      } else {
+        __builtin_nontemporal_store(t0, out + A0 + 256);
+        __builtin_nontemporal_store(t1, out + A0 + 257);
+        __builtin_nontemporal_store(t2, out + A0 + 258);
+      }
+    }
+  }
+}
+
 template <int TS, int D, int LAYOUT, bool VEC, bool BB>
 __global__ __launch_bounds__(256) void edm_tile_kernel(EdmArgs a, uint32_t lam0) {
   uint32_t I, J;
@@ -65,7 +149,13 @@ __global__ __launch_bounds__(256) void edm_tile_kernel(EdmArgs a, uint32_t lam0)
 
   float *__restrict__ out = a.D;
   const bool interior = (J < I) && (row0 + TS <= N);
-  if (interior) {
+  if constexpr (VEC && LAYOUT == kLayoutPacked) {
+    if (interior) {
+      packed_vec_rows<TS, D>(a, xs, row0, col0, lr, out);
+      return;
+    }
+  }
+  if (interior && (VEC ? LAYOUT == kLayoutFull : true)) {
 #pragma unroll 8
     for (int ps = 0; ps < PASSES; ++ps) {
       const int r = lr + ps * RPP;
@@ -124,7 +214,13 @@ static hipError_t launch_tiled_t(bool bb, const EdmArgs &a) {
 
 template <int TS, int D>
 static hipError_t launch_tiled_d(bool bb, const EdmArgs &a) {
-  if (a.layout == kLayoutPacked) return launch_tiled_t<TS, D, kLayoutPacked, false>(bb, a);
+  if (a.layout == kLayoutPacked) {
+    if constexpr (TS == 256) {
+      if ((reinterpret_cast<uintptr_t>(a.D) & 15) == 0)
+        return launch_tiled_t<TS, D, kLayoutPacked, true>(bb, a);
+    }
+    return launch_tiled_t<TS, D, kLayoutPacked, false>(bb, a);
+  }
   const bool aligned = (a.ldd % 4 == 0) && ((reinterpret_cast<uintptr_t>(a.D) & 15) == 0);
   return aligned ? launch_tiled_t<TS, D, kLayoutFull, true>(bb, a)
                  : launch_tiled_t<TS, D, kLayoutFull, false>(bb, a);
