@@ -128,7 +128,7 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx,
  * in the paper; it differentiates the EDM of Sec. IV, Eq. (17).
  *   X      device, N x d FP32, pitch ldx.    dD device, `layout` (pitch ldd).
  *   dX     device, N x d FP32, row pitch d, overwritten.
- *   rho    tile edge: 0 (autotuned), 64 or 128.
+ *   rho    tile edge: 0 (autotuned), 64, 128 or 256 (256: dD 16-byte aligned).
  *   deterministic  1: per-tile partial sums in the workspace, reduced in a
  *          fixed order (bitwise reproducible); 0: partial sums added with
  *          atomics (no workspace, order-dependent last bits).

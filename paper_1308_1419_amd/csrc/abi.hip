@@ -235,9 +235,10 @@ size_t tdmap_workspace_size(int32_t op, int64_t N, int32_t d, int32_t num_sets, 
     case TDMAP_OP_BACKWARD:
       if (!flags || d > 4) return 0;
       if (rho == 0)
-        return std::max(tdmap::backward_workspace_bytes(N, d, 64),
-                        tdmap::backward_workspace_bytes(N, d, 128));
-      if (rho != 64 && rho != 128) return 0;
+        return std::max({tdmap::backward_workspace_bytes(N, d, 64),
+                         tdmap::backward_workspace_bytes(N, d, 128),
+                         tdmap::backward_workspace_bytes(N, d, 256)});
+      if (rho != 64 && rho != 128 && rho != 256) return 0;
       return tdmap::backward_workspace_bytes(N, d, rho);
     case TDMAP_OP_BATCHED:
       if (num_sets < 0) return 0;
@@ -313,8 +314,10 @@ int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx, const 
   int st = validate_edm_common(X, N, d, ldx, dD, ldd, layout);
   if (st != TDMAP_OK) return st;
   if (N > 0 && dX == nullptr) return TDMAP_ERR_INVALID;
-  if (rho != 0 && rho != 64 && rho != 128) return TDMAP_ERR_INVALID;
+  if (rho != 0 && rho != 64 && rho != 128 && rho != 256) return TDMAP_ERR_INVALID;
   if (d > 4) return TDMAP_ERR_UNSUPPORTED;
+  const bool dd_aligned = (reinterpret_cast<uintptr_t>(dD) & 15) == 0;
+  if (rho == 256 && !dd_aligned) return TDMAP_ERR_UNSUPPORTED;
   if (N == 0) return TDMAP_OK;
   const uint64_t nb = ceil_div((uint64_t)N, rho ? (uint64_t)rho : 64);
   if (tri(nb) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
@@ -331,7 +334,9 @@ int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx, const 
     const TuneKey key(TDMAP_OP_BACKWARD, 0, 0, d, size_bucket(N));
     ts = tuned_lookup(key);
     if (ts == 0) {
-      ts = autotune({64, 128}, s, [&](int c) { return tdmap::launch_backward(c, a); }, &st);
+      std::vector<int> cands{64, 128};
+      if (dd_aligned) cands.push_back(256);
+      ts = autotune(cands, s, [&](int c) { return tdmap::launch_backward(c, a); }, &st);
       if (st != TDMAP_OK) return st;
       tuned_store(key, ts);
     }

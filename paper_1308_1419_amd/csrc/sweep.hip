@@ -45,46 +45,89 @@ __device__ __forceinline__ void load_pt(const float *__restrict__ X, int64_t ldx
   for (int k = 0; k < D; ++k) v[k] = X[p * ldx + k];
 }
 
+// One wave writes SW_G consecutive 1 KB pieces (SW_G float4 stores per
+// lane, each covering 256 consecutive positions).  When the wave's first
+// cell lies in a row of at least SW_G * 256 cells, its positions cover at
+// most two rows: the two row points are uniform (scalar loads) and every
+// column point load is issued before any arithmetic, so one memory latency
+// covers the whole 4 KB.  Short rows (the first few hundred) and the tail
+// of the array take a per-lane stepping path.
+constexpr int SW_G = 4;
+constexpr int SW_WAVE = 256 * SW_G;       // positions per wave
+constexpr int SW_BLOCK = 4 * SW_WAVE;     // positions per work-group
+
 template <int D>
 __global__ __launch_bounds__(256) void edm_sweep_kernel(const float *__restrict__ X, int64_t N,
                                                         int64_t ldx, float *__restrict__ out,
                                                         uint64_t total, uint64_t e_base) {
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint64_t ew = e_base + (uint64_t)blockIdx.x * 1024 + (uint64_t)w * 256;
+  const uint64_t ew = e_base + (uint64_t)blockIdx.x * SW_BLOCK + (uint64_t)w * SW_WAVE;
   if (ew >= total) return;
   uint64_t iw, jw;
   g_lambda64(ew, iw, jw);
   const uint32_t l = threadIdx.x & 63;
-  const uint64_t e0 = ew + 4 * l;
-  if (e0 >= total) return;
-  uint64_t i = iw, j = jw + 4 * l;
-  while (j > i) {
-    j -= i + 1;
-    ++i;
-  }
-  float xi[D];
-  load_pt<D>(X, ldx, i, xi);
-  float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (iw + 1 >= (uint64_t)SW_WAVE && ew + SW_WAVE <= total) {
+    const uint64_t i1 = iw + 1 < (uint64_t)N ? iw + 1 : iw;  // row below (may be unused)
+    float xa[D], xb[D];
+    load_pt<D>(X, ldx, iw, xa);
+    load_pt<D>(X, ldx, i1, xb);
+    float xj[SW_G][4][D];
+    bool lo[SW_G][4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (e0 + q >= total) break;
-    if (j > i) {  // next row
-      ++i;
-      j = 0;
-      load_pt<D>(X, ldx, i, xi);
+    for (int g = 0; g < SW_G; ++g)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t j = jw + 256 * g + 4 * l + q;
+        lo[g][q] = j <= iw;
+        load_pt<D>(X, ldx, lo[g][q] ? j : j - iw - 1, xj[g][q]);
+      }
+#pragma unroll
+    for (int g = 0; g < SW_G; ++g) {
+      f4 o;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float xi[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) xi[k] = lo[g][q] ? xa[k] : xb[k];
+        o[q] = pair_dist<D>(xi, xj[g][q]);
+      }
+      __builtin_nontemporal_store(o, reinterpret_cast<f4 *>(out + ew + 256 * g + 4 * l));
     }
-    float xj[D];
-    load_pt<D>(X, ldx, j, xj);
-    v[q] = pair_dist<D>(xi, xj);
-    ++j;
+    return;
   }
-  if (e0 + 4 <= total) {
-    f4 o = {v[0], v[1], v[2], v[3]};
-    __builtin_nontemporal_store(o, reinterpret_cast<f4 *>(out + e0));
-  } else {
+  // general path: each lane steps from the wave's first cell to its own
+  for (int g = 0; g < SW_G; ++g) {
+    const uint64_t e0 = ew + 256 * g + 4 * l;
+    if (e0 >= total) break;
+    uint64_t i = iw, j = jw + 256 * g + 4 * l;
+    while (j > i) {
+      j -= i + 1;
+      ++i;
+    }
+    float xi[D];
+    load_pt<D>(X, ldx, i, xi);
+    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (e0 + q < total) __builtin_nontemporal_store(v[q], out + e0 + q);
+    for (int q = 0; q < 4; ++q) {
+      if (e0 + q >= total) break;
+      if (j > i) {  // next row
+        ++i;
+        j = 0;
+        load_pt<D>(X, ldx, i, xi);
+      }
+      float xj[D];
+      load_pt<D>(X, ldx, j, xj);
+      v[q] = pair_dist<D>(xi, xj);
+      ++j;
+    }
+    if (e0 + 4 <= total) {
+      f4 o = {v[0], v[1], v[2], v[3]};
+      __builtin_nontemporal_store(o, reinterpret_cast<f4 *>(out + e0));
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (e0 + q < total) __builtin_nontemporal_store(v[q], out + e0 + q);
+    }
   }
 }
 
@@ -162,11 +205,11 @@ __global__ __launch_bounds__(256) void edm_batched_sweep_kernel(BatchArgs a) {
 template <int D>
 static hipError_t launch_sweep_t(const EdmArgs &a) {
   const uint64_t total = (uint64_t)a.N * (uint64_t)(a.N + 1) / 2;
-  const uint64_t per_launch = (uint64_t)1024 * (((uint64_t)1 << 31) / 256);
+  const uint64_t per_launch = (uint64_t)SW_BLOCK * (((uint64_t)1 << 31) / 256);
   for (uint64_t b = 0; b < total; b += per_launch) {
     const uint64_t c = total - b < per_launch ? total - b : per_launch;
-    hipLaunchKernelGGL(edm_sweep_kernel<D>, dim3((uint32_t)((c + 1023) / 1024)), dim3(256), 0,
-                       a.stream, a.X, a.N, a.ldx, a.D, b + c, b);
+    hipLaunchKernelGGL(edm_sweep_kernel<D>, dim3((uint32_t)((c + SW_BLOCK - 1) / SW_BLOCK)),
+                       dim3(256), 0, a.stream, a.X, a.N, a.ldx, a.D, b + c, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -43,9 +43,10 @@ def _full_from_packed(dD, N, fill=np.nan):
     return F
 
 
-@pytest.mark.parametrize("rho", [64, 128, 0])
+@pytest.mark.parametrize("rho", [64, 128, 256, 0])
 @pytest.mark.parametrize("det", [True, False])
-@pytest.mark.parametrize("N,d", [(1, 3), (2, 3), (3, 1), (37, 2), (300, 3), (1000, 4), (1100, 3)])
+@pytest.mark.parametrize("N,d", [(1, 3), (2, 3), (3, 1), (37, 2), (300, 3), (1000, 4), (1100, 3),
+                                 (1300, 2)])
 def test_backward_packed(rho, det, N, d):
     _require_gpu()
     X = synth.uniform_points(N, d, seed=40 + N + d)
@@ -69,7 +70,7 @@ def test_backward_full_layout_ignores_upper_triangle(det):
     Fp = np.full((N, N + 3), np.nan, dtype=np.float32)
     Fp[:, :N] = F                            # and a pitch that is not N
     Xd = torch.from_numpy(X).cuda()
-    for rho in (64, 128):
+    for rho in (64, 128, 256):
         got = tdmap.edm_backward(Xd, torch.from_numpy(Fp).cuda(), layout="full", rho=rho,
                                  deterministic=det, ldd=N + 3)
         torch.cuda.synchronize()
@@ -85,11 +86,29 @@ def test_backward_deterministic_bitwise():
     dD = np.random.default_rng(5).standard_normal(oedm.tri(N)).astype(np.float32)
     Xd = torch.from_numpy(X).cuda()
     dDd = torch.from_numpy(dD).cuda()
-    for rho in (64, 128):
+    for rho in (64, 128, 256):
         a = tdmap.edm_backward(Xd, dDd, rho=rho, deterministic=True)
         b = tdmap.edm_backward(Xd, dDd, rho=rho, deterministic=True)
         torch.cuda.synchronize()
         assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+def test_backward_unaligned_dD_pointer():
+    # the 16-byte-load tile needs an aligned dD; an offset view is refused
+    # for rho = 256 and handled by the other tiles under autotuning
+    _require_gpu()
+    N = 700
+    X = synth.uniform_points(N, 3, seed=14)
+    dD = np.random.default_rng(6).standard_normal(oedm.tri(N)).astype(np.float32)
+    buf = torch.empty(oedm.tri(N) + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = torch.from_numpy(dD).cuda()
+    view = buf[1:]
+    Xd = torch.from_numpy(X).cuda()
+    with pytest.raises(tdmap.TdmapError):
+        tdmap.edm_backward(Xd, view, rho=256, deterministic=True)
+    got = tdmap.edm_backward(Xd, view, rho=0, deterministic=True)
+    torch.cuda.synchronize()
+    _check_grad(got.cpu().numpy(), oedm.edm_backward64(X, dD), "unaligned dD")
 
 
 def test_backward_coincident_points_and_zero_gradient():
