@@ -151,9 +151,11 @@ int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx,
  *   point_off  device, S+1 int64, non-decreasing, point_off[0] = 0.
  *   out_off    device, S+1 int64, out_off[s+1] - out_off[s] =
  *              n_s(n_s+1)/2 with n_s = point_off[s+1] - point_off[s].
- *   rho        1: one-cell blocks, a persistent linear sweep of the
- *              concatenated packed output (D_cat 16-byte aligned);
- *              64 or 128: persistent walk over TS x TS tiles;
+ *   rho        1: one-cell blocks: a fixed grid sweeps the concatenated
+ *              packed output in 4 KB chunks, grid-stride (D_cat 16-byte
+ *              aligned);
+ *              64 or 128: a persistent grid walks TS x TS tiles in
+ *              contiguous ranges;
  *              0: autotuned.
  *   workspace  device, tdmap_workspace_size(TDMAP_OP_BATCHED, 0, d, S, rho, 0)
  *              bytes.

@@ -364,7 +364,7 @@ int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets, const int
   // rho = 1: persistent linear sweep of the concatenated packed output;
   // 64 / 128: persistent walk over the prefix-summed tile space
   auto run = [&](int c) {
-    return c == 1 ? tdmap::launch_batched_sweep(a, 8) : tdmap::launch_batched(c, a);
+    return c == 1 ? tdmap::launch_batched_sweep(a, 64) : tdmap::launch_batched(c, a);
   };
   int ts = rho;
   int st = TDMAP_OK;
@@ -372,9 +372,9 @@ int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets, const int
     const TuneKey key(TDMAP_OP_BATCHED, 0, 0, d, size_bucket(num_sets));
     ts = tuned_lookup(key);
     if (ts == 0) {
-      // the linear sweep (rho = 1) re-reads each set's points for every row
-      // it touches and loses to the tile walks; it is only run on request
-      ts = autotune({64, 128}, s, run, &st);
+      std::vector<int> cands{64, 128};
+      if (aligned) cands.insert(cands.begin(), 1);
+      ts = autotune(cands, s, run, &st);
       if (st != TDMAP_OK) return st;
       tuned_store(key, ts);
     }

@@ -131,73 +131,120 @@ __global__ __launch_bounds__(256) void edm_sweep_kernel(const float *__restrict_
   }
 }
 
-// Batched: positions [0, out_off[S]) of the concatenated packed triangles,
-// swept by a persistent grid.  Work-group b owns a contiguous run of
-// 1024-position pieces; the set of a position comes from out_off (one
-// binary search per wave, then forward steps), so nothing is read on the
-// host.
+// Batched: positions [0, out_off[S]) of the concatenated packed triangles.
+// Waves take 1024-position chunks in grid-stride order (chunk c, then
+// c + 4 * gridDim.x, ...), so the work-groups in flight always cover one
+// compact window of the output and the few sets it spans stay in cache.
+// The set of a chunk comes from out_off by a galloping search from the
+// wave's previous set; nothing is read on the host.  Chunks inside one set
+// whose first cell lies in a row of at least 1024 cells take the two-row
+// fast path of the single-set sweep; the rest step lane by lane.
+__device__ __forceinline__ int32_t set_of(const int64_t *__restrict__ oo, int32_t S, int32_t s,
+                                          uint64_t e) {
+  if ((uint64_t)oo[s + 1] > e) return s;
+  // gallop: find hi with oo[hi] > e
+  int32_t lo = s + 1, step = 1;
+  while (lo + step < S && (uint64_t)oo[lo + step] <= e) {
+    lo += step;
+    step <<= 1;
+  }
+  int32_t hi = lo + step < S ? lo + step : S;  // oo[hi] > e (oo[S] = total > e)
+  // largest t in [lo, hi) with oo[t] <= e
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if ((uint64_t)oo[mid] <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 template <int D>
-__global__ __launch_bounds__(256) void edm_batched_sweep_kernel(BatchArgs a) {
-  const int64_t *__restrict__ oo = a.out_off;
-  const uint64_t total = (uint64_t)oo[a.num_sets];
-  const uint64_t pieces = (total + 1023) / 1024;
-  const uint64_t per = (pieces + gridDim.x - 1) / gridDim.x;
-  const uint64_t p_lo = (uint64_t)blockIdx.x * per;
-  const uint64_t p_hi = p_lo + per < pieces ? p_lo + per : pieces;
-  if (p_lo >= p_hi) return;
+__global__ __launch_bounds__(256) void edm_batched_sweep_kernel(
+    const float *__restrict__ X, const int64_t *__restrict__ point_off,
+    const int64_t *__restrict__ oo, int32_t S, float *__restrict__ out) {
+  const uint64_t total = (uint64_t)oo[S];
+  const uint64_t chunks = (total + SW_WAVE - 1) / SW_WAVE;
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t l = threadIdx.x & 63;
-  // set of the wave's first position
-  const uint64_t e_first = p_lo * 1024 + (uint64_t)w * 256;
-  int32_t s0 = 0, s1 = a.num_sets;
-  while (s1 - s0 > 1) {
-    const int32_t mid = (s0 + s1) >> 1;
-    if ((uint64_t)oo[mid] <= e_first) s0 = mid; else s1 = mid;
-  }
-  int32_t sw = s0;
-  float *__restrict__ out = a.D;
-  for (uint64_t p = p_lo; p < p_hi; ++p) {
-    const uint64_t ew = p * 1024 + (uint64_t)w * 256;
-    if (ew >= total) break;
-    while ((uint64_t)oo[sw + 1] <= ew) ++sw;
-    const uint64_t e0 = ew + 4 * l;
-    if (e0 >= total) continue;
-    int32_t s = sw;
-    while ((uint64_t)oo[s + 1] <= e0) ++s;
-    uint64_t i, j;
-    g_lambda64(e0 - (uint64_t)oo[s], i, j);
-    int64_t n = a.point_off[s + 1] - a.point_off[s];
-    const float *__restrict__ Xs = a.X + a.point_off[s] * D;
-    float xi[D];
-    load_pt<D>(Xs, D, i, xi);
-    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  int32_t sw = 0;
+  for (uint64_t c = (uint64_t)blockIdx.x * 4 + w; c < chunks; c += (uint64_t)gridDim.x * 4) {
+    const uint64_t ew = c * SW_WAVE;
+    sw = set_of(oo, S, sw, ew);
+    const uint64_t o0 = (uint64_t)oo[sw];
+    const int64_t p0 = point_off[sw];
+    const float *__restrict__ Xs = X + p0 * D;
+    uint64_t iw, jw;
+    g_lambda64(ew - o0, iw, jw);
+    if (iw + 1 >= (uint64_t)SW_WAVE && ew + SW_WAVE <= (uint64_t)oo[sw + 1]) {
+      const int64_t n = point_off[sw + 1] - p0;
+      const uint64_t i1 = iw + 1 < (uint64_t)n ? iw + 1 : iw;
+      float xa[D], xb[D];
+      load_pt<D>(Xs, D, iw, xa);
+      load_pt<D>(Xs, D, i1, xb);
+      float xj[SW_G][4][D];
+      bool lo[SW_G][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (e0 + q >= total) break;
-      if (j > i) {
-        ++i;
-        j = 0;
-        if ((int64_t)i >= n) {  // first row of the next non-empty set
-          do {
-            ++s;
-          } while ((uint64_t)oo[s + 1] <= e0 + q);
-          i = 0;
-          n = a.point_off[s + 1] - a.point_off[s];
-          Xs = a.X + a.point_off[s] * D;
+      for (int g = 0; g < SW_G; ++g)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint64_t j = jw + 256 * g + 4 * l + q;
+          lo[g][q] = j <= iw;
+          load_pt<D>(Xs, D, lo[g][q] ? j : j - iw - 1, xj[g][q]);
         }
-        load_pt<D>(Xs, D, i, xi);
+#pragma unroll
+      for (int g = 0; g < SW_G; ++g) {
+        f4 o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float xi[D];
+#pragma unroll
+          for (int k = 0; k < D; ++k) xi[k] = lo[g][q] ? xa[k] : xb[k];
+          o[q] = pair_dist<D>(xi, xj[g][q]);
+        }
+        __builtin_nontemporal_store(o, reinterpret_cast<f4 *>(out + ew + 256 * g + 4 * l));
       }
-      float xj[D];
-      load_pt<D>(Xs, D, j, xj);
-      v[q] = pair_dist<D>(xi, xj);
-      ++j;
+      continue;
     }
-    if (e0 + 4 <= total) {
-      f4 o = {v[0], v[1], v[2], v[3]};
-      __builtin_nontemporal_store(o, reinterpret_cast<f4 *>(out + e0));
-    } else {
-      for (int q = 0; q < 4; ++q)
-        if (e0 + q < total) __builtin_nontemporal_store(v[q], out + e0 + q);
+    // general path: lane by lane, crossing rows and sets
+    for (int g = 0; g < SW_G; ++g) {
+      const uint64_t e0 = ew + 256 * g + 4 * l;
+      if (e0 >= total) break;
+      int32_t s = sw;
+      while ((uint64_t)oo[s + 1] <= e0) ++s;
+      uint64_t i, j;
+      g_lambda64(e0 - (uint64_t)oo[s], i, j);
+      int64_t n = point_off[s + 1] - point_off[s];
+      const float *__restrict__ Xl = X + point_off[s] * D;
+      float xi[D];
+      load_pt<D>(Xl, D, i, xi);
+      float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (e0 + q >= total) break;
+        if (j > i) {
+          ++i;
+          j = 0;
+          if ((int64_t)i >= n) {  // first row of the next non-empty set
+            do {
+              ++s;
+            } while ((uint64_t)oo[s + 1] <= e0 + q);
+            i = 0;
+            n = point_off[s + 1] - point_off[s];
+            Xl = X + point_off[s] * D;
+          }
+          load_pt<D>(Xl, D, i, xi);
+        }
+        float xj[D];
+        load_pt<D>(Xl, D, j, xj);
+        v[q] = pair_dist<D>(xi, xj);
+        ++j;
+      }
+      if (e0 + 4 <= total) {
+        f4 o = {v[0], v[1], v[2], v[3]};
+        __builtin_nontemporal_store(o, reinterpret_cast<f4 *>(out + e0));
+      } else {
+        for (int q = 0; q < 4; ++q)
+          if (e0 + q < total) __builtin_nontemporal_store(v[q], out + e0 + q);
+      }
     }
   }
 }
@@ -245,13 +292,17 @@ hipError_t launch_batched_sweep(const BatchArgs &a, int wgs_per_cu) {
       g_sweep_cus = 256;
   }
   const dim3 grid((uint32_t)(g_sweep_cus * wgs_per_cu));
+#define TD_BSWEEP(DD)                                                                      \
+  hipLaunchKernelGGL(edm_batched_sweep_kernel<DD>, grid, dim3(256), 0, a.stream, a.X,     \
+                     a.point_off, a.out_off, a.num_sets, a.D)
   switch (a.d) {
-    case 1: hipLaunchKernelGGL(edm_batched_sweep_kernel<1>, grid, dim3(256), 0, a.stream, a); break;
-    case 2: hipLaunchKernelGGL(edm_batched_sweep_kernel<2>, grid, dim3(256), 0, a.stream, a); break;
-    case 3: hipLaunchKernelGGL(edm_batched_sweep_kernel<3>, grid, dim3(256), 0, a.stream, a); break;
-    case 4: hipLaunchKernelGGL(edm_batched_sweep_kernel<4>, grid, dim3(256), 0, a.stream, a); break;
+    case 1: TD_BSWEEP(1); break;
+    case 2: TD_BSWEEP(2); break;
+    case 3: TD_BSWEEP(3); break;
+    case 4: TD_BSWEEP(4); break;
     default: return hipErrorInvalidValue;
   }
+#undef TD_BSWEEP
   return hipGetLastError();
 }
 
