@@ -76,138 +76,129 @@ __device__ __forceinline__ float exact_dist(const float *__restrict__ X, int64_t
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// Writes the 128 x 128 tile held in LDS to the packed output.  Each wave
-// owns 32 tile rows and writes two per instruction (one per half-wave).
-// Packed row i's segment [col0, col0 + 128) starts sh = (i(i+1)/2 + col0)
-// mod 4 positions past a 16-byte boundary; half-wave lane h stores the
-// aligned chunk at columns col0 - sh + 4h .. + 3, read back from LDS at that
-// shift.  Lane 0 of each half-wave writes the 4 - sh head cells and the sh
-// tail cells one by one (the neighbouring tiles write the rest of those two
-// chunks).  Diagonal and edge rows go cell by cell.
-__device__ __forceinline__ void store_tile_rows(const float (*tileD)[kGramTile + 4], int64_t row0,
-                                                int64_t col0, int64_t N, bool diag,
-                                                float *__restrict__ out) {
-  const int w = threadIdx.x >> 6;
-  const int l = threadIdx.x & 63;
-  const int h = l & 31;
-  const bool full_rows = !diag && row0 + kGramTile <= N;
-  for (int p = 0; p < 16; ++p) {
-    const int r = w * 32 + 2 * p + (l >> 5);
-    const int64_t i = row0 + r;
-    if (i >= N) continue;
-    const uint64_t first = tri64((uint64_t)i) + (uint64_t)col0;
-    if (full_rows) {
-      const int sh = (int)(first & 3);
-      const uint64_t A0 = first - (uint64_t)sh;
-      if (h > 0 || sh == 0) {
-        const int c = 4 * h - sh;
-        f4 v = {tileD[r][c], tileD[r][c + 1], tileD[r][c + 2], tileD[r][c + 3]};
-        __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(out + A0 + 4 * h));
-      } else {
-        for (int q = sh; q < 4; ++q) __builtin_nontemporal_store(tileD[r][q - sh], out + A0 + q);
-        for (int q = 0; q < sh; ++q)
-          __builtin_nontemporal_store(tileD[r][kGramTile - sh + q], out + A0 + kGramTile + q);
-      }
-    } else {
-      // last valid column of this row inside the tile
-      const int64_t jmax = (diag ? i : N - 1) - col0;
-      for (int c = h; c < kGramTile; c += 32)
-        if (c <= jmax) __builtin_nontemporal_store(tileD[r][c], out + first + c);
-    }
-  }
-}
+// Each wave owns 32 whole rows of the 128 x 128 tile: four 32 x 32
+// v_mfma_f32_32x32x16_bf16 accumulators (one per 32-column block).  Its
+// distances go, 16 rows at a time, through a wave-private LDS slice and are
+// written as packed rows with 16-byte stores; no work-group barrier is
+// needed, so the four waves run independently.
+//
+// Store layout: a half-wave writes one 128-cell row segment.  Packed row i's
+// segment [col0, col0 + 128) starts sh = (i(i+1)/2 + col0) mod 4 positions
+// past a 16-byte boundary; lane h stores the aligned chunk at columns
+// col0 - sh + 4h .. + 3, read from LDS at that shift.  Lane 0 of the
+// half-wave writes the 4 - sh head cells and the sh tail cells one by one
+// (the neighbouring tiles write the rest of those two chunks).  Diagonal and
+// edge rows go cell by cell.
+constexpr int kGramRows = 16;  // rows staged per step and wave
 
-__global__ __launch_bounds__(256) void gram_tile_kernel(GramArgs a, uint32_t lam0) {
+__global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t lam0) {
   uint32_t I, J;
   g_lambda(lam0 + blockIdx.x, I, J);
-  const int t = threadIdx.x;
-  const int w = t >> 6;
-  const int l = t & 63;
-  const int wr = w >> 1;
-  const int wc = w & 1;
-  const int64_t r0 = (int64_t)I * kGramTile + wr * 64;
-  const int64_t c0 = (int64_t)J * kGramTile + wc * 64;
-  const int KP = a.KP;
-  const uint16_t *__restrict__ Xb = a.Xb;
-  // the upper-right quadrant of a diagonal tile lies above the diagonal:
-  // its wave skips the products but still stores its share of the rows
-  const bool above = I == J && wr < wc;
-
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[bi][bj][v] = 0.0f;
-
-  // lane l supplies row (l % 32) of each 32-row block and the 8 features
-  // [8 (l / 32), 8 (l / 32) + 8) of each 16-feature step; B uses the same
-  // assignment for its points, so the product is x_i . x_j.
+  const int w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63;
   const int lr = l & 31;
   const int lk = (l >> 5) * 8;
-  for (int k = 0; k < (above ? 0 : KP); k += 16) {
-    bf16x8 av[2], bv[2];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      av[b] = *reinterpret_cast<const bf16x8 *>(Xb + (r0 + b * 32 + lr) * KP + k + lk);
-      bv[b] = *reinterpret_cast<const bf16x8 *>(Xb + (c0 + b * 32 + lr) * KP + k + lk);
-    }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
-  }
-
-  // accumulator v of a 32 x 32 block holds row (v/4)*8 + (l/32)*4 + v%4 and
-  // column l % 32.  The norms of every row and column this lane touches are
-  // loaded up front (the padded norm array covers every tile row).
   const int64_t N = a.N;
-  float nr[2][16];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int v = 0; v < 16; ++v)
-      nr[bi][v] = a.nrm[r0 + bi * 32 + (v >> 2) * 8 + (l >> 5) * 4 + (v & 3)];
-  float nc[2];
-#pragma unroll
-  for (int bj = 0; bj < 2; ++bj) nc[bj] = a.nrm[c0 + bj * 32 + lr];
+  const int64_t row0 = (int64_t)I * kGramTile;
+  const int64_t col0 = (int64_t)J * kGramTile;
+  const int64_t rw = row0 + 32 * w;  // this wave's first row
+  const bool diag = I == J;
+  // on a diagonal tile, column blocks right of this wave's rows are above
+  // the diagonal
+  const int nbj = diag ? w + 1 : 4;
+  const int KP = a.KP;
+  const uint16_t *__restrict__ Xb = a.Xb;
 
-  // distances go to an LDS copy of the tile first: sqrt(G) for every pair
-  // above the recompute threshold, then (rare: the diagonal and
-  // near-duplicate pairs) the exact FP32 difference form for the others
-  __shared__ float tileD[kGramTile][kGramTile + 4];
-  const int tr0 = wr * 64;
-  const int tc0 = wc * 64;
-  uint64_t need = 0;
+  float nr[16];
 #pragma unroll
-  for (int bj = 0; bj < 2; ++bj) {
+  for (int v = 0; v < 16; ++v) nr[v] = a.nrm[rw + (v >> 2) * 8 + (l >> 5) * 4 + (v & 3)];
+  float nc[4];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
+  for (int bj = 0; bj < 4; ++bj) nc[bj] = a.nrm[col0 + bj * 32 + lr];
+
+  f32x16 acc[4];
 #pragma unroll
-      for (int v = 0; v < 16 && !above; ++v) {
-        const int rr = bi * 32 + (v >> 2) * 8 + (l >> 5) * 4 + (v & 3);
-        const float sn = nr[bi][v] + nc[bj];
-        const float G = __builtin_fmaf(-2.0f, acc[bi][bj][v], sn);
-        if (G <= kGramTheta * sn) need |= (uint64_t)1 << ((bj * 2 + bi) * 16 + v);
-        tileD[tr0 + rr][tc0 + bj * 32 + lr] = __builtin_amdgcn_sqrtf(__builtin_fmaxf(G, 0.0f));
+  for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[bj][v] = 0.0f;
+  // lane l supplies row (l % 32) of a 32-row block and the 8 features
+  // [8 (l / 32), 8 (l / 32) + 8) of each 16-feature step; B uses the same
+  // assignment for its points, so the product is x_i . x_j.
+  for (int k = 0; k < KP; k += 16) {
+    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Xb + (rw + lr) * KP + k + lk);
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      if (bj < nbj) {
+        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Xb + (col0 + bj * 32 + lr) * KP + k + lk);
+        acc[bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[bj], 0, 0, 0);
       }
     }
   }
-  while (need) {
-    const int b = __builtin_ctzll(need);
-    need &= need - 1;
-    const int bj = b >> 5;
-    const int bi = (b >> 4) & 1;
-    const int v = b & 15;
-    const int rr = bi * 32 + (v >> 2) * 8 + (l >> 5) * 4 + (v & 3);
-    const int64_t i = r0 + rr;
-    const int64_t j = c0 + bj * 32 + lr;
-    if (i < N && j <= i) tileD[tr0 + rr][tc0 + bj * 32 + lr] = exact_dist(a.X, a.ldx, a.d, i, j);
+
+  __shared__ float stage[4][kGramRows][kGramTile + 4];
+  float(*st)[kGramTile + 4] = stage[w];
+  float *__restrict__ out = a.D;
+  const int h = l & 31;
+  const bool full_rows = !diag && row0 + kGramTile <= N;
+#pragma unroll
+  for (int vh = 0; vh < 2; ++vh) {
+    // accumulator v of a 32 x 32 block holds row (v/4)*8 + (l/32)*4 + v%4
+    // and column l % 32; v in [8 vh, 8 vh + 8) are the rows 16 vh .. +15
+    bool any = false;
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+#pragma unroll
+      for (int v = 8 * vh; v < 8 * vh + 8; ++v) {
+        const int rr = (v >> 2) * 8 + (l >> 5) * 4 + (v & 3) - 16 * vh;
+        const float sn = nr[v] + nc[bj];
+        const float G = __builtin_fmaf(-2.0f, acc[bj][v], sn);
+        const bool rec = G <= kGramTheta * sn;
+        any |= rec;
+        // a pair below the threshold is marked -1 and filled in below
+        st[rr][bj * 32 + lr] = rec ? -1.0f : __builtin_amdgcn_sqrtf(G);
+      }
+    }
+    if (any) {
+      // rare: the diagonal and near-duplicate pairs, exact FP32 difference
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) {
+#pragma unroll
+        for (int v = 8 * vh; v < 8 * vh + 8; ++v) {
+          const int rr = (v >> 2) * 8 + (l >> 5) * 4 + (v & 3) - 16 * vh;
+          if (st[rr][bj * 32 + lr] < 0.0f) {
+            const int64_t i = rw + 16 * vh + rr;
+            const int64_t j = col0 + bj * 32 + lr;
+            st[rr][bj * 32 + lr] = (i < N && j <= i) ? exact_dist(a.X, a.ldx, a.d, i, j) : 0.0f;
+          }
+        }
+      }
+    }
+    // the wave reads back its own LDS writes: no barrier needed
+#pragma unroll 2
+    for (int p = 0; p < kGramRows / 2; ++p) {
+      const int r = 2 * p + (l >> 5);
+      const int64_t i = rw + 16 * vh + r;
+      if (i >= N) continue;
+      const uint64_t first = tri64((uint64_t)i) + (uint64_t)col0;
+      if (full_rows) {
+        const int sh = (int)(first & 3);
+        const uint64_t A0 = first - (uint64_t)sh;
+        if (h > 0 || sh == 0) {
+          const int c = 4 * h - sh;
+          f4 v4 = {st[r][c], st[r][c + 1], st[r][c + 2], st[r][c + 3]};
+          __builtin_nontemporal_store(v4, reinterpret_cast<f4 *>(out + A0 + 4 * h));
+        } else {
+          for (int q = sh; q < 4; ++q) __builtin_nontemporal_store(st[r][q - sh], out + A0 + q);
+          for (int q = 0; q < sh; ++q)
+            __builtin_nontemporal_store(st[r][kGramTile - sh + q], out + A0 + kGramTile + q);
+        }
+      } else {
+        const int64_t jmax = (diag ? i : N - 1) - col0;
+        for (int c = h; c < kGramTile; c += 32)
+          if (c <= jmax) __builtin_nontemporal_store(st[r][c], out + first + c);
+      }
+    }
   }
-  __syncthreads();
-  store_tile_rows(tileD, (int64_t)I * kGramTile, (int64_t)J * kGramTile, N, I == J, a.D);
 }
 
 size_t gram_workspace_bytes(int64_t N, int d) {
