@@ -198,6 +198,59 @@ def row_batched(torch, tdmap, synth):
             "rho": tdmap.tdmap_tuned_rho(tdmap.OP_BATCHED, 0, 0, 3, 4096)}
 
 
+def first_map_failure(torch, tdmap, variant, chunk=1 << 27):
+    """Smallest lambda < 2^32 where the map under `variant` breaks the
+    row-major succession (0,0), (1,0), (1,1), (2,0), ... or None.  Uses no
+    oracle: the succession from lambda = 0 defines the numbering."""
+    out = torch.empty((chunk, 2), dtype=torch.int32, device="cuda")
+    prev = None
+    for lam0 in range(0, 1 << 32, chunk):
+        tdmap.map_blocks_variant(lam0, chunk, variant, out=out)
+        i = out[:, 0].to(torch.int64) & 0xFFFFFFFF
+        j = out[:, 1].to(torch.int64) & 0xFFFFFFFF
+        if prev is None:
+            if int(i[0]) != 0 or int(j[0]) != 0:
+                return 0
+        else:
+            pi, pj = prev
+            ok0 = (int(i[0]) == pi and int(j[0]) == pj + 1) or \
+                  (int(i[0]) == pi + 1 and int(j[0]) == 0 and pj == pi)
+            if not ok0:
+                return lam0
+        ok = ((i[1:] == i[:-1]) & (j[1:] == j[:-1] + 1)) | \
+             ((i[1:] == i[:-1] + 1) & (j[1:] == 0) & (j[:-1] == i[:-1]))
+        bad = torch.nonzero(~ok)
+        if bad.numel():
+            return lam0 + int(bad[0, 0]) + 1
+        prev = (int(i[-1]), int(j[-1]))
+    return None
+
+
+def row_mapcost(torch, tdmap, synth):
+    """The paper's dummy kernel (map + filter, no EDM) for every strategy at
+    N = 30000 and rho = 8, 16, 32, the LTM row variants at rho = 16, and where
+    the uncorrected variants first name a wrong cell."""
+    N = 30000
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    res = {}
+    for rho in (8, 16, 32):
+        row = {}
+        for s in ("ltm", "bb", "utm", "rb", "rec"):
+            row[s] = _med_ms(lambda s=s: tdmap.dummy(s, N, rho, sink=sink), 10) * 1e3
+        for s in list(row):
+            row[s] = {"us": row[s], "I_vs_bb": row["bb"] / row[s]}
+        res[f"rho{rho}"] = row
+    var = {}
+    t_bb = res["rho16"]["bb"]["us"]
+    for v, name in ((0, "ltm_fixup"), (1, "ltm_x_sqrtf"), (2, "ltm_r_rsq_eps")):
+        t = _med_ms(lambda v=v: tdmap.dummy("ltm", N, 16, variant=v, sink=sink), 10) * 1e3
+        I = t_bb / t
+        var[name] = {"us": t, "I_vs_bb": I, "k": 2.0 / I,
+                     "first_wrong_lambda": first_map_failure(torch, tdmap, v) if v else None}
+    res["ltm_variants_rho16"] = var
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +278,7 @@ def main():
         import torch
         from paper_1308_1419_amd import synth, tdmap
         fn = {"edm_n1024_d3_full": row_small, "stress_n20000_d3": row_stress,
+              "mapcost_n30000": row_mapcost,
               "gram_n100000_d64_packed": row_gram,
               "batched_s4096_n64_4096_d3": row_batched}[args.row]
         print(json.dumps({args.row: fn(torch, tdmap, synth)}), flush=True)
@@ -322,7 +376,8 @@ def main():
         del D
         torch.cuda.empty_cache()
         rows = {}
-        for name, fn in (("edm_n1024_d3_full", row_small), ("stress_n20000_d3", row_stress),
+        for name, fn in (("edm_n1024_d3_full", row_small), ("mapcost_n30000", row_mapcost),
+                         ("stress_n20000_d3", row_stress),
                          ("gram_n100000_d64_packed", row_gram),
                          ("batched_s4096_n64_4096_d3", row_batched)):
             log(f"row {name} ...")

@@ -196,6 +196,34 @@ int tdmap_waste_counts(int32_t strategy, int64_t N, int32_t rho, int64_t out[3])
 int tdmap_count_waste(int32_t strategy, int64_t N, int32_t rho,
                       uint64_t *counts, void *stream);
 
+/*
+ * The same map under the paper's three ways of taking the row (Sec. III-A),
+ * for measuring their accuracy: variant 0 is the exact map above; 1 is
+ * LTM-X, floor(sqrtf(1/4 + 2 lambda) - 1/2) with the default single-precision
+ * square root; 2 is LTM-R, sqrt(x) = x * rsq(x) (Eq. (16)) with
+ * epsilon = 1e-4 added before the floor.  Variants 1 and 2 are not corrected:
+ * past some lambda they can name the wrong row (and j is then computed from
+ * that row's start, wrapping as an unsigned value).
+ * Errors: INVALID for an unknown variant or a NULL ij; UNSUPPORTED past 2^32.
+ */
+int tdmap_map_blocks_variant(uint64_t lambda0, uint64_t count, int32_t variant, uint32_t *ij,
+                             void *stream);
+
+/*
+ * The paper's dummy kernel (Sec. III-A, Sec. IV): the strategy's launch with
+ * rho x rho blocks where every thread only computes its cell (i, j) and
+ * applies the strategy's filters.  It measures the cost of the space of
+ * computation itself.  The paper writes i + j to a fixed address; here the
+ * write happens only when i + j equals `never` (pass a value no cell has,
+ * e.g. 0xffffffff), which keeps the map live without every thread storing to
+ * one address.  `variant` selects the LTM row computation as in
+ * tdmap_map_blocks_variant (must be 0 for other strategies).
+ *   sink  device, one uint32 (written only if some cell has i + j == never).
+ * rho must be 8, 16 or 32.  Nothing else is written.
+ */
+int tdmap_dummy(int32_t strategy, int32_t variant, int64_t N, int32_t rho, uint32_t never,
+                uint32_t *sink, void *stream);
+
 /* Tile edge the autotuner has chosen for a call with rho = 0, or 0 if that
  * configuration has not been tuned yet.  `strategy` and `layout` are those
  * of the call (ignored for TDMAP_OP_BACKWARD / TDMAP_OP_BATCHED); `size` is

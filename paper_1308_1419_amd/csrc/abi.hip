@@ -388,6 +388,35 @@ int tdmap_waste_counts(int32_t strategy, int64_t N, int32_t rho, int64_t out[3])
   return waste_closed_form(strategy, N, rho, out) ? TDMAP_OK : TDMAP_ERR_INVALID;
 }
 
+int tdmap_map_blocks_variant(uint64_t lambda0, uint64_t count, int32_t variant, uint32_t *ij,
+                             void *stream) {
+  if (variant < 0 || variant > 2) return TDMAP_ERR_INVALID;
+  if (count == 0) return TDMAP_OK;
+  if (ij == nullptr) return TDMAP_ERR_INVALID;
+  if (lambda0 > ((uint64_t)1 << 32) || count > ((uint64_t)1 << 32) - lambda0)
+    return TDMAP_ERR_UNSUPPORTED;
+  TD_HIP(tdmap::launch_map_blocks_variant(lambda0, count, variant, ij, (hipStream_t)stream),
+         "tdmap_map_blocks_variant");
+  return TDMAP_OK;
+}
+
+int tdmap_dummy(int32_t strategy, int32_t variant, int64_t N, int32_t rho, uint32_t never,
+                uint32_t *sink, void *stream) {
+  if (sink == nullptr || N < 0) return TDMAP_ERR_INVALID;
+  if (strategy < TDMAP_LTM || strategy > TDMAP_REC) return TDMAP_ERR_INVALID;
+  if (variant < 0 || variant > 2 || (variant != 0 && strategy != TDMAP_LTM)) return TDMAP_ERR_INVALID;
+  if (!is_cell_rho(rho)) return TDMAP_ERR_UNSUPPORTED;
+  const uint64_t nb = ceil_div((uint64_t)N, (uint64_t)rho);
+  if (tri(nb) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
+  if (strategy == TDMAP_UTM && tri((uint64_t)N) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
+  tdmap::EdmArgs a{nullptr, N, 1, 1, nullptr, 0, TDMAP_PACKED, (hipStream_t)stream};
+  a.sink = sink;
+  a.never = never;
+  a.variant = variant;
+  TD_HIP(tdmap::launch_dummy(strategy, rho, a), "tdmap_dummy");
+  return TDMAP_OK;
+}
+
 int tdmap_count_waste(int32_t strategy, int64_t N, int32_t rho, uint64_t *counts, void *stream) {
   if (counts == nullptr || N < 0) return TDMAP_ERR_INVALID;
   if (strategy < TDMAP_LTM || strategy > TDMAP_REC) return TDMAP_ERR_INVALID;

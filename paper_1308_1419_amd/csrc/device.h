@@ -41,6 +41,31 @@ __device__ __forceinline__ void g_lambda(uint32_t lam, uint32_t &i, uint32_t &j)
   j = (uint32_t)(lam - t);
 }
 
+// The paper's three ways of taking the row of g(lambda) (Sec. III-A), kept
+// for the mapping-cost measurements; only variant 0 is exact everywhere.
+//   0: the fix-up map above (rsq guess + integer correction);
+//   1: LTM-X, i = floor(sqrtf(1/4 + 2 lambda) - 1/2) with the default
+//      (correctly rounded) single-precision square root, no correction;
+//   2: LTM-R, sqrt(x) = x * rsq(x) (Eq. (16)) with epsilon = 1e-4 added
+//      before the floor, no correction.
+// Variants 1 and 2 can be off by one row once lambda is large; j is then
+// computed from the wrong row start (it wraps as an unsigned value).
+__device__ __forceinline__ void g_lambda_variant(uint32_t lam, int variant, uint32_t &i,
+                                                 uint32_t &j) {
+  if (variant == 0) {
+    g_lambda(lam, i, j);
+    return;
+  }
+  const float x = __builtin_fmaf(2.0f, (float)lam, 0.25f);
+  float r;
+  if (variant == 1)
+    r = sqrtf(x) - 0.5f;
+  else
+    r = x * __builtin_amdgcn_rsqf(x) - 0.5f + 1e-4f;
+  i = (uint32_t)__builtin_floorf(__builtin_fmaxf(r, 0.0f));
+  j = (uint32_t)(lam - (uint32_t)tri64(i));
+}
+
 // Squared distance then square root, in a fixed operation order:
 // s = t_0^2, s = fma(t_k, t_k, s) for k = 1..d-1, D = v_sqrt_f32(s).
 // v_sqrt_f32 is accurate to 1 ulp; with d <= 4 the whole value is within a

@@ -85,10 +85,12 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // Store layout: a half-wave writes one 128-cell row segment.  Packed row i's
 // segment [col0, col0 + 128) starts sh = (i(i+1)/2 + col0) mod 4 positions
 // past a 16-byte boundary; lane h stores the aligned chunk at columns
-// col0 - sh + 4h .. + 3, read from LDS at that shift.  Lane 0 of the
-// half-wave writes the 4 - sh head cells and the sh tail cells one by one
-// (the neighbouring tiles write the rest of those two chunks).  Diagonal and
-// edge rows go cell by cell.
+// col0 - sh + 4h .. + 3, read from LDS at that shift.  The cells of the two
+// partial chunks at the ends of each segment (the neighbouring tiles write
+// the rest of those chunks) are gathered one row per lane and written with
+// four instructions per 16 rows: single-lane stores per row would multiply
+// the store instruction count several times over.  Diagonal and edge rows
+// go cell by cell.
 constexpr int kGramRows = 16;  // rows staged per step and wave
 
 __global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t lam0) {
@@ -174,25 +176,39 @@ __global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t 
       }
     }
     // the wave reads back its own LDS writes: no barrier needed
+    if (full_rows) {
+      // whole aligned chunks, two rows per instruction
 #pragma unroll 2
-    for (int p = 0; p < kGramRows / 2; ++p) {
-      const int r = 2 * p + (l >> 5);
-      const int64_t i = rw + 16 * vh + r;
-      if (i >= N) continue;
-      const uint64_t first = tri64((uint64_t)i) + (uint64_t)col0;
-      if (full_rows) {
+      for (int p = 0; p < kGramRows / 2; ++p) {
+        const int r = 2 * p + (l >> 5);
+        const uint64_t first = tri64((uint64_t)(rw + 16 * vh + r)) + (uint64_t)col0;
         const int sh = (int)(first & 3);
-        const uint64_t A0 = first - (uint64_t)sh;
         if (h > 0 || sh == 0) {
           const int c = 4 * h - sh;
           f4 v4 = {st[r][c], st[r][c + 1], st[r][c + 2], st[r][c + 3]};
-          __builtin_nontemporal_store(v4, reinterpret_cast<f4 *>(out + A0 + 4 * h));
-        } else {
-          for (int q = sh; q < 4; ++q) __builtin_nontemporal_store(st[r][q - sh], out + A0 + q);
-          for (int q = 0; q < sh; ++q)
-            __builtin_nontemporal_store(st[r][kGramTile - sh + q], out + A0 + kGramTile + q);
+          __builtin_nontemporal_store(v4, reinterpret_cast<f4 *>(out + first - sh + 4 * h));
         }
-      } else {
+      }
+      // the partial chunks at both ends of every row: the 4 - sh head cells
+      // (columns 0 .. 3 - sh) and the sh tail cells (columns 128 - sh .. 127),
+      // one row per lane, four instructions for all 16 rows
+      if (l < kGramRows) {
+        const uint64_t first = tri64((uint64_t)(rw + 16 * vh + l)) + (uint64_t)col0;
+        const int sh = (int)(first & 3);
+        if (sh != 0) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int c = q < 4 - sh ? q : kGramTile - 4 + q;
+            __builtin_nontemporal_store(st[l][c], out + first + c);
+          }
+        }
+      }
+    } else {
+      for (int p = 0; p < kGramRows / 2; ++p) {
+        const int r = 2 * p + (l >> 5);
+        const int64_t i = rw + 16 * vh + r;
+        if (i >= N) continue;
+        const uint64_t first = tri64((uint64_t)i) + (uint64_t)col0;
         const int64_t jmax = (diag ? i : N - 1) - col0;
         for (int c = h; c < kGramTile; c += 32)
           if (c <= jmax) __builtin_nontemporal_store(st[r][c], out + first + c);

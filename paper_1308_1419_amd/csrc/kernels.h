@@ -16,6 +16,10 @@ struct EdmArgs {
   int64_t ldd;
   int layout;
   hipStream_t stream;
+  // mapping-cost (dummy) kernels only
+  uint32_t *sink = nullptr;
+  uint32_t never = 0;
+  int variant = 0;
 };
 
 // g(lambda) for lambda0 .. lambda0 + count - 1 (caller checks the range).
@@ -24,6 +28,14 @@ hipError_t launch_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, hip
 // Paper-style launch: rho x rho threads, one cell per thread.  With
 // counts != nullptr the instrumented variant counts instead of storing.
 hipError_t launch_cell(int strategy, int rho, const EdmArgs &a, unsigned long long *counts);
+
+// The paper's dummy kernel for a strategy (map and filter only); for LTM,
+// a.variant picks the square root (0 exact fix-up, 1 sqrtf, 2 rsq + eps).
+hipError_t launch_dummy(int strategy, int rho, const EdmArgs &a);
+
+// g(lambda) export under a map variant (see g_lambda_variant).
+hipError_t launch_map_blocks_variant(uint64_t lambda0, uint64_t count, int variant, uint32_t *ij,
+                                     hipStream_t stream);
 
 // Coarsened tile launch (LTM on a 1D g(lambda) grid, or BB on an n x n grid).
 bool tiled_supported(int ts, int d);

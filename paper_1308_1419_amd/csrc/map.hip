@@ -18,6 +18,19 @@ __global__ __launch_bounds__(256) void map_blocks_kernel(uint64_t lambda0, uint6
   reinterpret_cast<uint2 *>(ij)[t] = v;
 }
 
+__global__ __launch_bounds__(256) void map_blocks_variant_kernel(uint64_t lambda0, uint64_t count,
+                                                                 int variant,
+                                                                 uint32_t *__restrict__ ij) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  uint32_t i, j;
+  g_lambda_variant((uint32_t)(lambda0 + t), variant, i, j);
+  uint2 v;
+  v.x = i;
+  v.y = j;
+  reinterpret_cast<uint2 *>(ij)[t] = v;
+}
+
 __global__ __launch_bounds__(256) void fill_kernel(float *__restrict__ p, uint64_t n, float v) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) p[t] = v;
@@ -31,6 +44,20 @@ hipError_t launch_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, hip
     const uint32_t blocks = (uint32_t)((c + 255) / 256);
     hipLaunchKernelGGL(map_blocks_kernel, dim3(blocks), dim3(256), 0, stream, lambda0 + done, c,
                        ij + 2 * done);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_map_blocks_variant(uint64_t lambda0, uint64_t count, int variant, uint32_t *ij,
+                                     hipStream_t stream) {
+  const uint64_t per_launch = (uint64_t)1 << 31;
+  for (uint64_t done = 0; done < count; done += per_launch) {
+    const uint64_t c = count - done < per_launch ? count - done : per_launch;
+    const uint32_t blocks = (uint32_t)((c + 255) / 256);
+    hipLaunchKernelGGL(map_blocks_variant_kernel, dim3(blocks), dim3(256), 0, stream,
+                       lambda0 + done, c, variant, ij + 2 * done);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -4,21 +4,28 @@
 // bit-identical values).  The maps are arithmetic only: no lookup tables,
 // no auxiliary global memory (the restriction of Sec. III-B).
 //
-// Each kernel has an instrumented twin (COUNT = true) that evaluates the
-// same map and filters, and counts blocks / fully idle blocks / idle
-// threads instead of storing.
+// Each kernel has two twins that evaluate the same map and filters: one
+// counts blocks / fully idle blocks / idle threads instead of storing, the
+// other is the paper's dummy kernel (Sec. III-A, Sec. IV), which measures
+// the cost of the map alone.
 #include "device.h"
 #include "kernels.h"
 
 namespace tdmap {
 
 enum { kLTM = 0, kBB = 1, kUTM = 2, kRB = 3, kREC = 4 };
+enum { kModeStore = 0, kModeCount = 1, kModeDummy = 2 };
 
-template <int D, int LAYOUT, bool COUNT>
+template <int D, int LAYOUT, int MODE>
 __device__ __forceinline__ void finish_cell(const EdmArgs &a, bool live, int64_t i, int64_t j,
                                             unsigned long long *counts) {
-  if constexpr (COUNT) {
+  if constexpr (MODE == kModeCount) {
     count_block(counts, live ? 1 : 0, (int)(blockDim.x * blockDim.y));
+  } else if constexpr (MODE == kModeDummy) {
+    // the mapping-cost kernel: the cell's i + j is "written" only when it
+    // equals a run-time value no cell has, which keeps every step of the map
+    // live without a store per thread to one address
+    if (live && (uint32_t)(i + j) == a.never) a.sink[0] = (uint32_t)(i + j);
   } else {
     if (live) a.D[out_index<LAYOUT>(i, j, a.ldd)] = cell_dist<D>(a.X, a.ldx, a.d, i, j);
   }
@@ -27,27 +34,30 @@ __device__ __forceinline__ void finish_cell(const EdmArgs &a, bool live, int64_t
 // LTM: a 1D grid of exactly n(n+1)/2 blocks; block lambda covers block row
 // and column g(lambda) (Sec. II-A, Eq. (2)).  Only the n diagonal blocks
 // (and the edge when rho does not divide N) filter threads.
-template <int D, int LAYOUT, bool COUNT>
+template <int D, int LAYOUT, int MODE>
 __global__ void ltm_cell_kernel(EdmArgs a, uint32_t lam0, unsigned long long *counts) {
   uint32_t bi, bj;
-  g_lambda(lam0 + blockIdx.x, bi, bj);
+  if constexpr (MODE == kModeDummy)
+    g_lambda_variant(lam0 + blockIdx.x, a.variant, bi, bj);
+  else
+    g_lambda(lam0 + blockIdx.x, bi, bj);
   const int64_t i = (int64_t)bi * blockDim.y + threadIdx.y;
   const int64_t j = (int64_t)bj * blockDim.x + threadIdx.x;
-  finish_cell<D, LAYOUT, COUNT>(a, i < a.N && j <= i, i, j, counts);
+  finish_cell<D, LAYOUT, MODE>(a, i < a.N && j <= i, i, j, counts);
 }
 
 // BB: an n x n grid (x = block column, y = block row).  A block above the
 // diagonal returns before computing any thread coordinate; the others keep
 // cells with j <= i < N (Sec. III-B).
-template <int D, int LAYOUT, bool COUNT>
+template <int D, int LAYOUT, int MODE>
 __global__ void bb_cell_kernel(EdmArgs a, unsigned long long *counts) {
   const uint32_t bx = blockIdx.x, by = blockIdx.y;
-  if constexpr (!COUNT) {
+  if constexpr (MODE == kModeStore) {
     if (bx > by) return;
   }
   const int64_t i = (int64_t)by * blockDim.y + threadIdx.y;
   const int64_t j = (int64_t)bx * blockDim.x + threadIdx.x;
-  finish_cell<D, LAYOUT, COUNT>(a, bx <= by && i < a.N && j <= i, i, j, counts);
+  finish_cell<D, LAYOUT, MODE>(a, bx <= by && i < a.N && j <= i, i, j, counts);
 }
 
 // UTM (Avril et al., Sec. III-B): thread k of a 1D grid takes the k-th pair
@@ -59,7 +69,7 @@ __global__ void bb_cell_kernel(EdmArgs a, unsigned long long *counts) {
 // row that is off by one.  The pair is half-turned onto the lower triangle
 // with the diagonal: (i, j) = (N - a, N + 1 - b), which keeps consecutive
 // threads on one output row.
-template <int D, int LAYOUT, bool COUNT>
+template <int D, int LAYOUT, int MODE>
 __global__ void utm_cell_kernel(EdmArgs a, uint64_t k0, unsigned long long *counts) {
   const uint32_t lanes = blockDim.x * blockDim.y;
   const uint64_t k = k0 + (uint64_t)blockIdx.x * lanes + threadIdx.y * blockDim.x + threadIdx.x;
@@ -86,7 +96,7 @@ __global__ void utm_cell_kernel(EdmArgs a, uint64_t k0, unsigned long long *coun
     // a thread stores nothing (the coverage tests would then fail)
     live = i >= 0 && i < N && j >= 0 && j <= i;
   }
-  finish_cell<D, LAYOUT, COUNT>(a, live, i, j, counts);
+  finish_cell<D, LAYOUT, MODE>(a, live, i, j, counts);
 }
 
 // RB (Jung et al., Sec. III-B): the threads form a rectangle; for even N
@@ -95,7 +105,7 @@ __global__ void utm_cell_kernel(EdmArgs a, uint64_t k0, unsigned long long *coun
 // (ty > tx): (i, j) = (ty - 1, tx); on or above: (N - 1 - ty, N - 1 - tx).
 // Odd N cuts at floor(N/2): N rows, floor(N/2)+1 columns, (ty, tx) when
 // ty >= tx, else (N - 1 - ty, N - tx).
-template <int D, int LAYOUT, bool COUNT>
+template <int D, int LAYOUT, int MODE>
 __global__ void rb_cell_kernel(EdmArgs a, unsigned long long *counts) {
   const int64_t N = a.N;
   const int64_t ty = (int64_t)blockIdx.y * blockDim.y + threadIdx.y;
@@ -122,7 +132,7 @@ __global__ void rb_cell_kernel(EdmArgs a, unsigned long long *counts) {
       j = N - tx;
     }
   }
-  finish_cell<D, LAYOUT, COUNT>(a, live, i, j, counts);
+  finish_cell<D, LAYOUT, MODE>(a, live, i, j, counts);
 }
 
 // REC (Ries et al., Sec. III-B), in block units: the side is padded to
@@ -132,7 +142,7 @@ __global__ void rb_cell_kernel(EdmArgs a, unsigned long long *counts) {
 // sits at block rows [(2q+1)s, (2q+2)s) and block columns [2qs, (2q+1)s)
 // (grid s x (s * 2^(k-1-l))).  Block coordinates are computed at run time,
 // not looked up.  Blocks past the real side nb are idle.
-template <int D, int LAYOUT, bool COUNT>
+template <int D, int LAYOUT, int MODE>
 __global__ void rec_cell_kernel(EdmArgs a, int mode, uint32_t side, uint32_t nb,
                                 unsigned long long *counts) {
   const uint32_t q = blockIdx.y / side;
@@ -149,12 +159,12 @@ __global__ void rec_cell_kernel(EdmArgs a, int mode, uint32_t side, uint32_t nb,
     blk_live = true;
   }
   blk_live = blk_live && R < nb;
-  if constexpr (!COUNT) {
+  if constexpr (MODE == kModeStore) {
     if (!blk_live) return;
   }
   const int64_t i = (int64_t)R * blockDim.y + threadIdx.y;
   const int64_t j = (int64_t)C * blockDim.x + threadIdx.x;
-  finish_cell<D, LAYOUT, COUNT>(a, blk_live && i < a.N && j <= i, i, j, counts);
+  finish_cell<D, LAYOUT, MODE>(a, blk_live && i < a.N && j <= i, i, j, counts);
 }
 
 // ---------------------------------------------------------------------------
@@ -175,7 +185,7 @@ static void rec_shape(uint32_t nb, uint32_t &m, uint32_t &k) {
   }
 }
 
-template <int D, int LAYOUT, bool COUNT>
+template <int D, int LAYOUT, int MODE>
 static hipError_t launch_cell_t(int strategy, int rho, const EdmArgs &a,
                                 unsigned long long *counts) {
   const dim3 blk(rho, rho);
@@ -189,14 +199,14 @@ static hipError_t launch_cell_t(int strategy, int rho, const EdmArgs &a,
       const uint64_t T = nb * (nb + 1) / 2;
       for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
         const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
-        hipLaunchKernelGGL((ltm_cell_kernel<D, LAYOUT, COUNT>), dim3((uint32_t)c), blk, 0,
+        hipLaunchKernelGGL((ltm_cell_kernel<D, LAYOUT, MODE>), dim3((uint32_t)c), blk, 0,
                            a.stream, a, (uint32_t)l0, counts);
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
       return e;
     }
     case kBB:
-      hipLaunchKernelGGL((bb_cell_kernel<D, LAYOUT, COUNT>), dim3((uint32_t)nb, (uint32_t)nb),
+      hipLaunchKernelGGL((bb_cell_kernel<D, LAYOUT, MODE>), dim3((uint32_t)nb, (uint32_t)nb),
                          blk, 0, a.stream, a, counts);
       return hipGetLastError();
     case kUTM: {
@@ -204,7 +214,7 @@ static hipError_t launch_cell_t(int strategy, int rho, const EdmArgs &a,
       const uint64_t blocks = (P + lanes - 1) / lanes;
       for (uint64_t b0 = 0; b0 < blocks; b0 += max_blocks) {
         const uint64_t c = blocks - b0 < max_blocks ? blocks - b0 : max_blocks;
-        hipLaunchKernelGGL((utm_cell_kernel<D, LAYOUT, COUNT>), dim3((uint32_t)c), blk, 0,
+        hipLaunchKernelGGL((utm_cell_kernel<D, LAYOUT, MODE>), dim3((uint32_t)c), blk, 0,
                            a.stream, a, b0 * lanes, counts);
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
@@ -216,20 +226,20 @@ static hipError_t launch_cell_t(int strategy, int rho, const EdmArgs &a,
       const uint32_t gx = (uint32_t)((cols + rho - 1) / rho);
       const uint32_t gy = (uint32_t)((rows + rho - 1) / rho);
       if (gx == 0 || gy == 0) return hipSuccess;
-      hipLaunchKernelGGL((rb_cell_kernel<D, LAYOUT, COUNT>), dim3(gx, gy), blk, 0, a.stream, a,
+      hipLaunchKernelGGL((rb_cell_kernel<D, LAYOUT, MODE>), dim3(gx, gy), blk, 0, a.stream, a,
                          counts);
       return hipGetLastError();
     }
     case kREC: {
       uint32_t m = 1, k = 0;
       rec_shape((uint32_t)nb, m, k);
-      hipLaunchKernelGGL((rec_cell_kernel<D, LAYOUT, COUNT>), dim3(m, m << k), blk, 0, a.stream,
+      hipLaunchKernelGGL((rec_cell_kernel<D, LAYOUT, MODE>), dim3(m, m << k), blk, 0, a.stream,
                          a, 0, m, (uint32_t)nb, counts);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       for (uint32_t lev = 0; lev < k; ++lev) {
         const uint32_t s = m << lev;
         const uint32_t squares = 1u << (k - 1 - lev);
-        hipLaunchKernelGGL((rec_cell_kernel<D, LAYOUT, COUNT>), dim3(s, s * squares), blk, 0,
+        hipLaunchKernelGGL((rec_cell_kernel<D, LAYOUT, MODE>), dim3(s, s * squares), blk, 0,
                            a.stream, a, 1, s, (uint32_t)nb, counts);
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
@@ -243,19 +253,24 @@ static hipError_t launch_cell_t(int strategy, int rho, const EdmArgs &a,
 template <int LAYOUT>
 static hipError_t launch_cell_layout(int strategy, int rho, const EdmArgs &a) {
   switch (a.d) {
-    case 1: return launch_cell_t<1, LAYOUT, false>(strategy, rho, a, nullptr);
-    case 2: return launch_cell_t<2, LAYOUT, false>(strategy, rho, a, nullptr);
-    case 3: return launch_cell_t<3, LAYOUT, false>(strategy, rho, a, nullptr);
-    case 4: return launch_cell_t<4, LAYOUT, false>(strategy, rho, a, nullptr);
-    default: return launch_cell_t<0, LAYOUT, false>(strategy, rho, a, nullptr);
+    case 1: return launch_cell_t<1, LAYOUT, kModeStore>(strategy, rho, a, nullptr);
+    case 2: return launch_cell_t<2, LAYOUT, kModeStore>(strategy, rho, a, nullptr);
+    case 3: return launch_cell_t<3, LAYOUT, kModeStore>(strategy, rho, a, nullptr);
+    case 4: return launch_cell_t<4, LAYOUT, kModeStore>(strategy, rho, a, nullptr);
+    default: return launch_cell_t<0, LAYOUT, kModeStore>(strategy, rho, a, nullptr);
   }
 }
 
 hipError_t launch_cell(int strategy, int rho, const EdmArgs &a, unsigned long long *counts) {
   if (a.N == 0) return hipSuccess;
-  if (counts) return launch_cell_t<1, kLayoutPacked, true>(strategy, rho, a, counts);
+  if (counts) return launch_cell_t<1, kLayoutPacked, kModeCount>(strategy, rho, a, counts);
   return a.layout == kLayoutFull ? launch_cell_layout<kLayoutFull>(strategy, rho, a)
                                  : launch_cell_layout<kLayoutPacked>(strategy, rho, a);
+}
+
+hipError_t launch_dummy(int strategy, int rho, const EdmArgs &a) {
+  if (a.N == 0) return hipSuccess;
+  return launch_cell_t<1, kLayoutPacked, kModeDummy>(strategy, rho, a, nullptr);
 }
 
 }  // namespace tdmap

@@ -67,6 +67,8 @@ def _load() -> ctypes.CDLL:
         "tdmap_workspace_size": ([i32, i64, i32, i32, i32, i32], sz),
         "tdmap_waste_counts": ([i32, i64, i32, vp], ctypes.c_int),
         "tdmap_count_waste": ([i32, i64, i32, vp, vp], ctypes.c_int),
+        "tdmap_map_blocks_variant": ([u64, u64, i32, vp, vp], ctypes.c_int),
+        "tdmap_dummy": ([i32, i32, i64, i32, ctypes.c_uint32, vp, vp], ctypes.c_int),
         "tdmap_tuned_rho": ([i32, i32, i32, i32, i64], i32),
         "tdmap_autotune_reset": ([], None),
         "tdmap_status_string": ([i32], ctypes.c_char_p),
@@ -83,6 +85,7 @@ def _load() -> ctypes.CDLL:
 EXPORTED = (
     "tdmap_map_blocks", "tdmap_edm", "tdmap_edm_backward", "tdmap_edm_batched",
     "tdmap_workspace_size", "tdmap_waste_counts", "tdmap_count_waste",
+    "tdmap_map_blocks_variant", "tdmap_dummy",
     "tdmap_tuned_rho", "tdmap_autotune_reset", "tdmap_status_string",
     "tdmap_last_error",
 )
@@ -138,6 +141,16 @@ def tdmap_count_waste(strategy: int, N: int, rho: int, counts: int, stream: int)
     _check(_load().tdmap_count_waste(strategy, N, rho, counts, stream), "tdmap_count_waste")
 
 
+def tdmap_map_blocks_variant(lambda0: int, count: int, variant: int, ij: int, stream: int) -> None:
+    _check(_load().tdmap_map_blocks_variant(lambda0, count, variant, ij, stream),
+           "tdmap_map_blocks_variant")
+
+
+def tdmap_dummy(strategy: int, variant: int, N: int, rho: int, never: int, sink: int,
+                stream: int) -> None:
+    _check(_load().tdmap_dummy(strategy, variant, N, rho, never, sink, stream), "tdmap_dummy")
+
+
 def tdmap_tuned_rho(op: int, strategy: int, layout: int, d: int, size: int) -> int:
     return int(_load().tdmap_tuned_rho(op, strategy, layout, d, size))
 
@@ -189,6 +202,24 @@ def map_blocks(lambda0: int, count: int, out=None):
         out = torch.empty((count, 2), dtype=torch.int32, device="cuda")
     tdmap_map_blocks(lambda0, count, out.data_ptr() if count else 0, _stream())
     return out
+
+
+def map_blocks_variant(lambda0: int, count: int, variant: int, out=None):
+    """g(lambda) under a row variant (0 exact, 1 LTM-X, 2 LTM-R + eps)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((count, 2), dtype=torch.int32, device="cuda")
+    tdmap_map_blocks_variant(lambda0, count, variant, out.data_ptr() if count else 0, _stream())
+    return out
+
+
+def dummy(strategy: str, N: int, rho: int, variant: int = 0, sink=None):
+    """The mapping-cost (dummy) kernel of a strategy; returns the sink."""
+    torch = _torch()
+    if sink is None:
+        sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    tdmap_dummy(STRATEGIES[strategy], variant, N, rho, 0xFFFFFFFF, sink.data_ptr(), _stream())
+    return sink
 
 
 def edm(X, layout: str = "full", strategy: str = "ltm", rho: int = 0,

@@ -68,6 +68,12 @@ def test_validation_rejects_before_launch(lib):
     # UTM's thread index is 32-bit: N(N+1)/2 must stay below 2^32
     assert L.tdmap_edm(8, 100000, 3, 3, 8, 100000, 0, tdmap.UTM, 16, 0, None, 0, None) \
         == tdmap.ERR_UNSUPPORTED
+    # map variants and the dummy kernel validate before launching
+    assert L.tdmap_map_blocks_variant(0, 10, 3, 8, None) == tdmap.ERR_INVALID
+    assert L.tdmap_map_blocks_variant(0, 10, 1, None, None) == tdmap.ERR_INVALID
+    assert L.tdmap_dummy(tdmap.BB, 1, 100, 16, 0, 8, None) == tdmap.ERR_INVALID
+    assert L.tdmap_dummy(0, 0, 100, 64, 0, 8, None) == tdmap.ERR_UNSUPPORTED
+    assert L.tdmap_dummy(0, 0, 100, 16, 0, None, None) == tdmap.ERR_INVALID
     # the instrumented count needs a paper-style rho
     assert L.tdmap_count_waste(0, 100, 64, 8, None) == tdmap.ERR_UNSUPPORTED
     assert L.tdmap_count_waste(0, 100, 16, None, None) == tdmap.ERR_INVALID
