@@ -161,6 +161,29 @@ def row_stress(torch, tdmap, synth):
             "bwd_rho": tdmap.tdmap_tuned_rho(tdmap.OP_BACKWARD, 0, 0, 3, N)}
 
 
+def row_strict(torch, tdmap, synth):
+    """30000 points, d = 3, the problem without the diagonal (Eq. (10)):
+    strictly lower packed output, linear sweep (positions mapped by the
+    no-diagonal g) and 256-cell tiles, beside the packed layout with the
+    diagonal."""
+    N = 30000
+    X = torch.from_numpy(synth.uniform_points(N, 3, seed=synth.workload_seed(2))).cuda()
+    S = torch.empty(N * (N - 1) // 2, dtype=torch.float32, device="cuda")
+    out = {"N": N, "pairs": S.numel()}
+    for rho in (1, 64, 128, 256):
+        t = _med_ms(lambda rho=rho: tdmap.edm(X, layout="strict", rho=rho, out=S), 20)
+        out[f"strict_rho{rho}_us"] = t * 1e3
+        out[f"strict_rho{rho}_hbm_frac"] = 4 * S.numel() / (t * 1e-3) / 1e9 / HBM_PEAK_GBS
+    del S
+    P = torch.empty(N * (N + 1) // 2, dtype=torch.float32, device="cuda")
+    for rho in (1, 256):
+        t = _med_ms(lambda rho=rho: tdmap.edm(X, layout="packed", rho=rho, out=P), 20)
+        out[f"packed_rho{rho}_us"] = t * 1e3
+        out[f"packed_rho{rho}_hbm_frac"] = 4 * P.numel() / (t * 1e-3) / 1e9 / HBM_PEAK_GBS
+    del P
+    return out
+
+
 def row_gram(torch, tdmap, synth):
     """100000 points, d = 64, BF16 Gram form on MFMA, packed output."""
     N, d = 100000, 64
@@ -278,7 +301,7 @@ def main():
         import torch
         from paper_1308_1419_amd import synth, tdmap
         fn = {"edm_n1024_d3_full": row_small, "stress_n20000_d3": row_stress,
-              "mapcost_n30000": row_mapcost,
+              "mapcost_n30000": row_mapcost, "strict_n30000_d3": row_strict,
               "gram_n100000_d64_packed": row_gram,
               "batched_s4096_n64_4096_d3": row_batched}[args.row]
         print(json.dumps({args.row: fn(torch, tdmap, synth)}), flush=True)
@@ -377,6 +400,7 @@ def main():
         torch.cuda.empty_cache()
         rows = {}
         for name, fn in (("edm_n1024_d3_full", row_small), ("mapcost_n30000", row_mapcost),
+                         ("strict_n30000_d3", row_strict),
                          ("stress_n20000_d3", row_stress),
                          ("gram_n100000_d64_packed", row_gram),
                          ("batched_s4096_n64_4096_d3", row_batched)):

@@ -30,6 +30,12 @@
  *                    left untouched.
  *     TDMAP_PACKED : N(N+1)/2 FP32, cell (i, j) at i(i+1)/2 + j (64-bit
  *                    offsets; ldd is ignored).
+ *     TDMAP_PACKED_STRICT : the problem without the diagonal (Sec. II-A,
+ *                    Eq. (10)): N(N-1)/2 FP32, cell (i, j), j < i, at
+ *                    i(i-1)/2 + j (64-bit offsets; ldd is ignored); this
+ *                    is the row-major strictly-lower pair list, e.g. a
+ *                    collision or interaction table.  With N = 1 there is
+ *                    no cell and the output pointer may be NULL.
  * - Inputs and outputs must not overlap (undefined behaviour otherwise).
  */
 #ifndef TDMAP_H
@@ -59,7 +65,7 @@ typedef enum {
     TDMAP_REC = 4   /* recursive partition of Ries et al.: a diagonal pass + k level launches (Sec. III-B) */
 } tdmap_strategy;
 
-typedef enum { TDMAP_FULL = 0, TDMAP_PACKED = 1 } tdmap_layout;
+typedef enum { TDMAP_FULL = 0, TDMAP_PACKED = 1, TDMAP_PACKED_STRICT = 2 } tdmap_layout;
 
 typedef enum {
     TDMAP_FP32 = 0,      /* difference form sqrt(sum_k (x_ik - x_jk)^2) in FP32 */
@@ -84,6 +90,15 @@ typedef enum { TDMAP_OP_EDM = 0, TDMAP_OP_BACKWARD = 1, TDMAP_OP_BATCHED = 2 } t
 int tdmap_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, void *stream);
 
 /*
+ * The map without the diagonal (Sec. II-A, Eq. (10)): lambda enumerates the
+ * cells (i, j), 0 <= j < i, row by row, i = floor(sqrt(1/4 + 2 lambda) + 1/2)
+ * and j = lambda - i(i-1)/2 (the column is taken from this enumeration's
+ * row start; with i(i+1)/2 as printed it would be negative).  Same exact
+ * fix-up, argument meaning and errors as tdmap_map_blocks.
+ */
+int tdmap_map_blocks_nodiag(uint64_t lambda0, uint64_t count, uint32_t *ij, void *stream);
+
+/*
  * Lower-triangular Euclidean distance map D_ij = sqrt(sum_k (x_ik - x_jk)^2),
  * 0 <= j <= i < N (the EDM problem of Sec. IV, Eq. (17)), computed by the
  * chosen space-of-computation strategy.
@@ -91,10 +106,12 @@ int tdmap_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, void *strea
  *   D        device, output in `layout` (pitch ldd for TDMAP_FULL).
  *   strategy one of tdmap_strategy.
  *   rho      the dimensional block size (Sec. II-A):
- *              1         : (LTM, TDMAP_PACKED, D 16-byte aligned) blocks of
- *                          one cell: g(lambda) maps every packed position
- *                          to its cell and the output is written as one
- *                          linear sweep, four positions per thread;
+ *              1         : (LTM, TDMAP_PACKED or TDMAP_PACKED_STRICT, D
+ *                          16-byte aligned) blocks of one cell: g(lambda)
+ *                          (Eq. (10) for the strict layout) maps every
+ *                          packed position to its cell and the output is
+ *                          written as one linear sweep, four positions per
+ *                          thread;
  *              8, 16, 32 : rho x rho threads per block, one cell per thread,
  *                          as the paper launches every strategy;
  *              64, 128, 256 : (LTM, BB) rho x rho cell tiles per 256-thread
@@ -102,6 +119,8 @@ int tdmap_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, void *strea
  *              0         : (LTM, BB) tile chosen by the autotuner.
  *   precision TDMAP_FP32 for every strategy; TDMAP_BF16_GRAM only with
  *            TDMAP_LTM, TDMAP_PACKED and rho = 0 or 128.
+ *   layout   TDMAP_PACKED_STRICT only with TDMAP_FP32, LTM or BB and
+ *            rho = 0, 1 (LTM), 64, 128 or 256.
  *   workspace device scratch of at least
  *            tdmap_workspace_size(TDMAP_OP_EDM, N, d, 0, rho, precision)
  *            bytes (0 for TDMAP_FP32; may then be NULL).
@@ -126,7 +145,8 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx,
  * a term being 0 where D = 0; diagonal cells of dD are ignored.  The tiles
  * are enumerated by g(lambda) as in the forward map.  This operation is not
  * in the paper; it differentiates the EDM of Sec. IV, Eq. (17).
- *   X      device, N x d FP32, pitch ldx.    dD device, `layout` (pitch ldd).
+ *   X      device, N x d FP32, pitch ldx.    dD device, `layout` (pitch ldd;
+ *          any of the three layouts).
  *   dX     device, N x d FP32, row pitch d, overwritten.
  *   rho    tile edge: 0 (autotuned), 64, 128 or 256 (256: dD 16-byte aligned).
  *   deterministic  1: per-tile partial sums in the workspace, reduced in a

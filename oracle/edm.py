@@ -9,7 +9,9 @@ once.  Nothing is blocked, fused or reordered beyond that.
 
 Layouts (the ones the library writes):
 * packed: cell (i, j), 0 <= j <= i < N, at index i(i+1)/2 + j;
-* full:   an N x N row-major matrix where only j <= i is defined.
+* full:   an N x N row-major matrix where only j <= i is defined;
+* strict: the problem without the diagonal (Sec. II-A, Eq. (10)): cell
+  (i, j), 0 <= j < i < N, at index i(i-1)/2 + j.
 """
 from __future__ import annotations
 
@@ -43,6 +45,18 @@ def edm64_packed(X: np.ndarray) -> np.ndarray:
     out = np.empty(tri(N), dtype=np.float64)
     for i in range(N):
         out[tri(i): tri(i) + i + 1] = edm64_row(X64, i)
+    return out
+
+
+def edm64_strict(X: np.ndarray) -> np.ndarray:
+    """All cells j < i, packed row-major without the diagonal: N(N-1)/2
+    FP64 values, cell (i, j) at i(i-1)/2 + j."""
+    X64 = _as64(X)
+    N = X64.shape[0]
+    out = np.empty(N * (N - 1) // 2 if N > 0 else 0, dtype=np.float64)
+    for i in range(1, N):
+        start = i * (i - 1) // 2
+        out[start: start + i] = edm64_row(X64, i)[:i]
     return out
 
 

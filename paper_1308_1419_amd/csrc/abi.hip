@@ -182,9 +182,12 @@ bool waste_closed_form(int strategy, int64_t N, int rho, int64_t out[3]) {
 int validate_edm_common(const float *X, int64_t N, int32_t d, int64_t ldx, const void *D,
                         int64_t ldd, int32_t layout) {
   if (N < 0 || d < 1 || ldx < d) return TDMAP_ERR_INVALID;
-  if (layout != TDMAP_FULL && layout != TDMAP_PACKED) return TDMAP_ERR_INVALID;
+  if (layout != TDMAP_FULL && layout != TDMAP_PACKED && layout != TDMAP_PACKED_STRICT)
+    return TDMAP_ERR_INVALID;
   if (N == 0) return TDMAP_OK;
-  if (X == nullptr || D == nullptr) return TDMAP_ERR_INVALID;
+  if (X == nullptr) return TDMAP_ERR_INVALID;
+  // without the diagonal a single point has no cell, so D may then be NULL
+  if (D == nullptr && !(layout == TDMAP_PACKED_STRICT && N == 1)) return TDMAP_ERR_INVALID;
   if (layout == TDMAP_FULL && ldd < N) return TDMAP_ERR_INVALID;
   return TDMAP_OK;
 }
@@ -222,6 +225,16 @@ int tdmap_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, void *strea
   if (lambda0 > ((uint64_t)1 << 32) || count > ((uint64_t)1 << 32) - lambda0)
     return TDMAP_ERR_UNSUPPORTED;
   TD_HIP(tdmap::launch_map_blocks(lambda0, count, ij, (hipStream_t)stream), "tdmap_map_blocks");
+  return TDMAP_OK;
+}
+
+int tdmap_map_blocks_nodiag(uint64_t lambda0, uint64_t count, uint32_t *ij, void *stream) {
+  if (count == 0) return TDMAP_OK;
+  if (ij == nullptr) return TDMAP_ERR_INVALID;
+  if (lambda0 > ((uint64_t)1 << 32) || count > ((uint64_t)1 << 32) - lambda0)
+    return TDMAP_ERR_UNSUPPORTED;
+  TD_HIP(tdmap::launch_map_blocks_nodiag(lambda0, count, ij, (hipStream_t)stream),
+         "tdmap_map_blocks_nodiag");
   return TDMAP_OK;
 }
 
@@ -269,8 +282,9 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int64
   }
   const bool tiled = !is_cell_rho(rho);
   if (tiled && strategy != TDMAP_LTM && strategy != TDMAP_BB) return TDMAP_ERR_UNSUPPORTED;
+  if (layout == TDMAP_PACKED_STRICT && !tiled) return TDMAP_ERR_UNSUPPORTED;
   if (tiled && d > 4) return TDMAP_ERR_UNSUPPORTED;
-  if (rho == 1 && (strategy != TDMAP_LTM || layout != TDMAP_PACKED ||
+  if (rho == 1 && (strategy != TDMAP_LTM || layout == TDMAP_FULL ||
                    (reinterpret_cast<uintptr_t>(D) & 15) != 0))
     return TDMAP_ERR_UNSUPPORTED;
   if (N == 0) return TDMAP_OK;

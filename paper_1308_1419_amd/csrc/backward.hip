@@ -373,6 +373,9 @@ template <int TS, int D>
 static hipError_t launch_bwd_d(const BwdArgs &a) {
   if (a.layout == kLayoutFull)
     return a.ws ? launch_bwd_t<TS, D, kLayoutFull, true>(a) : launch_bwd_t<TS, D, kLayoutFull, false>(a);
+  if (a.layout == kLayoutStrict)
+    return a.ws ? launch_bwd_t<TS, D, kLayoutStrict, true>(a)
+                : launch_bwd_t<TS, D, kLayoutStrict, false>(a);
   return a.ws ? launch_bwd_t<TS, D, kLayoutPacked, true>(a)
               : launch_bwd_t<TS, D, kLayoutPacked, false>(a);
 }

@@ -15,6 +15,7 @@ namespace tdmap {
 
 constexpr int kLayoutFull = 0;
 constexpr int kLayoutPacked = 1;
+constexpr int kLayoutStrict = 2;  // packed without the diagonal: i(i-1)/2 + j, j < i
 
 __device__ __forceinline__ uint64_t tri64(uint64_t i) { return i * (i + 1) >> 1; }
 
@@ -35,6 +36,28 @@ __device__ __forceinline__ void g_lambda(uint32_t lam, uint32_t &i, uint32_t &j)
     t -= (uint64_t)r + 1;  // T(r) = T(r+1) - (r+1)
   } else if (t + r + 1 <= lam) {
     t += (uint64_t)r + 1;  // T(r+1) = T(r) + r + 1
+    ++r;
+  }
+  i = r;
+  j = (uint32_t)(lam - t);
+}
+
+// The map without the diagonal (Sec. II-A, Eq. (10)): lambda enumerates the
+// cells j < i row by row, row i starting at S(i) = i(i-1)/2, and
+// i = floor(sqrt(1/4 + 2 lambda) + 1/2), j = lambda - S(i) (the column is
+// taken from the row start of this enumeration; see the readings of the
+// paper).  Same single-precision guess and integer fix-up as g_lambda.
+__device__ __forceinline__ void g_nodiag(uint32_t lam, uint32_t &i, uint32_t &j) {
+  const float x = __builtin_fmaf(2.0f, (float)lam, 0.25f);
+  const float s = x * __builtin_amdgcn_rsqf(x);
+  uint32_t r = (uint32_t)(s + 0.5f);
+  if (r == 0) r = 1;
+  uint64_t t = ((uint64_t)r * (r - 1)) >> 1;  // S(r)
+  if (t > lam) {
+    --r;
+    t -= r;  // S(r) = S(r+1) - r
+  } else if (t + r <= lam) {
+    t += r;  // S(r+1) = S(r) + r
     ++r;
   }
   i = r;
@@ -120,9 +143,18 @@ template <int LAYOUT>
 __device__ __forceinline__ uint64_t out_index(uint64_t i, uint64_t j, int64_t ldd) {
   if constexpr (LAYOUT == kLayoutFull) {
     return i * (uint64_t)ldd + j;
-  } else {
+  } else if constexpr (LAYOUT == kLayoutPacked) {
     return tri64(i) + j;
+  } else {
+    return ((i * (i - 1)) >> 1) + j;  // 0 for i = 0, which holds no cell
   }
+}
+
+// Whether cell (i, j) belongs to the layout's triangle (i < N is separate).
+template <int LAYOUT>
+__device__ __forceinline__ bool in_triangle(int64_t i, int64_t j) {
+  if constexpr (LAYOUT == kLayoutStrict) return j < i;
+  return j <= i;
 }
 
 // Launch statistics gathered by the instrumented kernels:

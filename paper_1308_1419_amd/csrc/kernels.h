@@ -24,6 +24,8 @@ struct EdmArgs {
 
 // g(lambda) for lambda0 .. lambda0 + count - 1 (caller checks the range).
 hipError_t launch_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, hipStream_t stream);
+hipError_t launch_map_blocks_nodiag(uint64_t lambda0, uint64_t count, uint32_t *ij,
+                                    hipStream_t stream);
 
 // Paper-style launch: rho x rho threads, one cell per thread.  With
 // counts != nullptr the instrumented variant counts instead of storing.

@@ -1,4 +1,5 @@
-// tdmap_map_blocks: g(lambda) for a range of block indices (Sec. II-A, Eq. (2)).
+// tdmap_map_blocks: g(lambda) for a range of block indices (Sec. II-A, Eq. (2));
+// tdmap_map_blocks_nodiag: the map without the diagonal (Eq. (10)).
 #include "device.h"
 #include "kernels.h"
 
@@ -6,12 +7,16 @@ namespace tdmap {
 
 // One lane per lambda.  Unlike the EDM kernels, lambda varies across the
 // wave here, so the fix-up compares run per lane.
+template <bool NODIAG>
 __global__ __launch_bounds__(256) void map_blocks_kernel(uint64_t lambda0, uint64_t count,
                                                          uint32_t *__restrict__ ij) {
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   uint32_t i, j;
-  g_lambda((uint32_t)(lambda0 + t), i, j);
+  if constexpr (NODIAG)
+    g_nodiag((uint32_t)(lambda0 + t), i, j);
+  else
+    g_lambda((uint32_t)(lambda0 + t), i, j);
   uint2 v;
   v.x = i;
   v.y = j;
@@ -36,18 +41,28 @@ __global__ __launch_bounds__(256) void fill_kernel(float *__restrict__ p, uint64
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) p[t] = v;
 }
 
-hipError_t launch_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, hipStream_t stream) {
+template <bool NODIAG>
+static hipError_t launch_map_t(uint64_t lambda0, uint64_t count, uint32_t *ij, hipStream_t stream) {
   // at most 2^32 lanes per launch: split the range
   const uint64_t per_launch = (uint64_t)1 << 31;
   for (uint64_t done = 0; done < count; done += per_launch) {
     const uint64_t c = count - done < per_launch ? count - done : per_launch;
     const uint32_t blocks = (uint32_t)((c + 255) / 256);
-    hipLaunchKernelGGL(map_blocks_kernel, dim3(blocks), dim3(256), 0, stream, lambda0 + done, c,
-                       ij + 2 * done);
+    hipLaunchKernelGGL(map_blocks_kernel<NODIAG>, dim3(blocks), dim3(256), 0, stream,
+                       lambda0 + done, c, ij + 2 * done);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, hipStream_t stream) {
+  return launch_map_t<false>(lambda0, count, ij, stream);
+}
+
+hipError_t launch_map_blocks_nodiag(uint64_t lambda0, uint64_t count, uint32_t *ij,
+                                    hipStream_t stream) {
+  return launch_map_t<true>(lambda0, count, ij, stream);
 }
 
 hipError_t launch_map_blocks_variant(uint64_t lambda0, uint64_t count, int variant, uint32_t *ij,

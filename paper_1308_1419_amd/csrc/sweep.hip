@@ -9,6 +9,10 @@
 // wave's 256 positions span at most a couple of rows); each lane then
 // steps from the wave's first cell to its own.
 //
+// Without the diagonal (strict layout, index i(i-1)/2 + j, j < i) the same
+// sweep maps positions with the paper's no-diagonal map (Sec. II-A,
+// Eq. (10)); row i then holds i cells instead of i + 1.
+//
 // The batched variant sweeps the concatenation of every set's packed
 // triangle; positions past the end of a set continue in the next one.
 #include "device.h"
@@ -38,6 +42,25 @@ __device__ __forceinline__ void g_lambda64(uint64_t lam, uint64_t &i, uint64_t &
   j = lam - t;
 }
 
+// Eq. (10) for 64-bit lambda: row i starts at S(i) = i(i-1)/2.
+__device__ __forceinline__ void g_nodiag64(uint64_t lam, uint64_t &i, uint64_t &j) {
+  const float x = __builtin_fmaf(2.0f, (float)lam, 0.25f);
+  const float s = x * __builtin_amdgcn_rsqf(x);
+  uint64_t r = (uint64_t)(s + 0.5f);
+  if (r == 0) r = 1;
+  uint64_t t = (r * (r - 1)) >> 1;
+  while (t > lam) {
+    --r;
+    t -= r;
+  }
+  while (t + r <= lam) {
+    t += r;
+    ++r;
+  }
+  i = r;
+  j = lam - t;
+}
+
 template <int D>
 __device__ __forceinline__ void load_pt(const float *__restrict__ X, int64_t ldx, uint64_t p,
                                         float (&v)[D]) {
@@ -56,17 +79,23 @@ constexpr int SW_G = 4;
 constexpr int SW_WAVE = 256 * SW_G;       // positions per wave
 constexpr int SW_BLOCK = 4 * SW_WAVE;     // positions per work-group
 
-template <int D>
+template <int D, bool STRICT>
 __global__ __launch_bounds__(256) void edm_sweep_kernel(const float *__restrict__ X, int64_t N,
                                                         int64_t ldx, float *__restrict__ out,
                                                         uint64_t total, uint64_t e_base) {
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t ew = e_base + (uint64_t)blockIdx.x * SW_BLOCK + (uint64_t)w * SW_WAVE;
   if (ew >= total) return;
+  // cells in row i
+  auto row_len = [](uint64_t i) -> uint64_t { return STRICT ? i : i + 1; };
   uint64_t iw, jw;
-  g_lambda64(ew, iw, jw);
+  if constexpr (STRICT)
+    g_nodiag64(ew, iw, jw);
+  else
+    g_lambda64(ew, iw, jw);
   const uint32_t l = threadIdx.x & 63;
-  if (iw + 1 >= (uint64_t)SW_WAVE && ew + SW_WAVE <= total) {
+  const uint64_t len_w = row_len(iw);
+  if (len_w >= (uint64_t)SW_WAVE && ew + SW_WAVE <= total) {
     const uint64_t i1 = iw + 1 < (uint64_t)N ? iw + 1 : iw;  // row below (may be unused)
     float xa[D], xb[D];
     load_pt<D>(X, ldx, iw, xa);
@@ -78,8 +107,8 @@ __global__ __launch_bounds__(256) void edm_sweep_kernel(const float *__restrict_
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint64_t j = jw + 256 * g + 4 * l + q;
-        lo[g][q] = j <= iw;
-        load_pt<D>(X, ldx, lo[g][q] ? j : j - iw - 1, xj[g][q]);
+        lo[g][q] = j < len_w;
+        load_pt<D>(X, ldx, lo[g][q] ? j : j - len_w, xj[g][q]);
       }
 #pragma unroll
     for (int g = 0; g < SW_G; ++g) {
@@ -100,8 +129,8 @@ __global__ __launch_bounds__(256) void edm_sweep_kernel(const float *__restrict_
     const uint64_t e0 = ew + 256 * g + 4 * l;
     if (e0 >= total) break;
     uint64_t i = iw, j = jw + 256 * g + 4 * l;
-    while (j > i) {
-      j -= i + 1;
+    while (j >= row_len(i)) {
+      j -= row_len(i);
       ++i;
     }
     float xi[D];
@@ -110,7 +139,7 @@ __global__ __launch_bounds__(256) void edm_sweep_kernel(const float *__restrict_
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (e0 + q >= total) break;
-      if (j > i) {  // next row
+      if (j >= row_len(i)) {  // next row
         ++i;
         j = 0;
         load_pt<D>(X, ldx, i, xi);
@@ -249,13 +278,14 @@ __global__ __launch_bounds__(256) void edm_batched_sweep_kernel(
   }
 }
 
-template <int D>
+template <int D, bool STRICT>
 static hipError_t launch_sweep_t(const EdmArgs &a) {
-  const uint64_t total = (uint64_t)a.N * (uint64_t)(a.N + 1) / 2;
+  const uint64_t total = STRICT ? (uint64_t)a.N * (uint64_t)(a.N - 1) / 2
+                                : (uint64_t)a.N * (uint64_t)(a.N + 1) / 2;
   const uint64_t per_launch = (uint64_t)SW_BLOCK * (((uint64_t)1 << 31) / 256);
   for (uint64_t b = 0; b < total; b += per_launch) {
     const uint64_t c = total - b < per_launch ? total - b : per_launch;
-    hipLaunchKernelGGL(edm_sweep_kernel<D>, dim3((uint32_t)((c + SW_BLOCK - 1) / SW_BLOCK)),
+    hipLaunchKernelGGL((edm_sweep_kernel<D, STRICT>), dim3((uint32_t)((c + SW_BLOCK - 1) / SW_BLOCK)),
                        dim3(256), 0, a.stream, a.X, a.N, a.ldx, a.D, b + c, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -264,17 +294,18 @@ static hipError_t launch_sweep_t(const EdmArgs &a) {
 }
 
 bool sweep_supported(const EdmArgs &a) {
-  return a.layout == kLayoutPacked && a.d >= 1 && a.d <= 4 &&
+  return (a.layout == kLayoutPacked || a.layout == kLayoutStrict) && a.d >= 1 && a.d <= 4 &&
          (reinterpret_cast<uintptr_t>(a.D) & 15) == 0;
 }
 
 hipError_t launch_sweep(const EdmArgs &a) {
   if (a.N == 0) return hipSuccess;
+  const bool strict = a.layout == kLayoutStrict;
   switch (a.d) {
-    case 1: return launch_sweep_t<1>(a);
-    case 2: return launch_sweep_t<2>(a);
-    case 3: return launch_sweep_t<3>(a);
-    case 4: return launch_sweep_t<4>(a);
+    case 1: return strict ? launch_sweep_t<1, true>(a) : launch_sweep_t<1, false>(a);
+    case 2: return strict ? launch_sweep_t<2, true>(a) : launch_sweep_t<2, false>(a);
+    case 3: return strict ? launch_sweep_t<3, true>(a) : launch_sweep_t<3, false>(a);
+    case 4: return strict ? launch_sweep_t<4, true>(a) : launch_sweep_t<4, false>(a);
     default: return hipErrorInvalidValue;
   }
 }

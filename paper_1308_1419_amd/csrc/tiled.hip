@@ -25,16 +25,20 @@ namespace tdmap {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Interior tile rows in the packed layout with 16-byte stores (TS = 256:
-// one row per wave and pass).  Packed row i starts at i(i+1)/2, so the
-// tile's row segment [col0, col0 + 256) begins s = (i(i+1)/2 + col0) mod 4
-// positions past a 16-byte boundary.  Lane l stores the aligned chunk
+// one row per wave and pass).  Packed row i starts at R(i) = i(i+1)/2 (or
+// i(i-1)/2 without the diagonal), so the tile's row segment
+// [col0, col0 + 256) begins s = (R(i) + col0) mod 4 positions past a
+// 16-byte boundary.  Lane l stores the aligned chunk
 // holding columns col0 - s + 4l .. col0 - s + 4l + 3; for lanes 1..63 those
 // all lie in the segment, so each of them needs the points of columns
 // col0 + 4l - 3 .. col0 + 4l + 3 (kept in registers) and picks four of them
-// by s, which is uniform across the wave.  Lane 0 writes the 4 - s head
-// cells and the s tail cells (col0 + 256 - s .. col0 + 255) one by one; the
-// neighbouring tiles write the rest of the two shared chunks.
-template <int TS, int D>
+// by s, which is uniform across the wave.  The 4 - s head cells and the s
+// tail cells (col0 + 256 - s .. col0 + 255) go out in one 4-byte store
+// instruction from lanes 0..5: lanes 0..2 own chunk positions 1..3 of the
+// first chunk, lanes 3..5 positions 0..2 of the chunk after the last full
+// one, and each keeps the point it needs for every s.  The neighbouring
+// tiles write the rest of the two shared chunks.
+template <int TS, int D, int LAYOUT>
 __device__ __forceinline__ void packed_vec_rows(const EdmArgs &a, const float *xs, int64_t row0,
                                                 int64_t col0, int lr, float *__restrict__ out) {
   static_assert(TS == 256, "one tile row per wave");
@@ -46,11 +50,21 @@ __device__ __forceinline__ void packed_vec_rows(const EdmArgs &a, const float *x
 #pragma unroll
     for (int k = 0; k < D; ++k) win[o][k] = c >= 0 ? a.X[c * a.ldx + k] : 0.0f;
   }
-  float tail[3][D];
+  // edge lane e = l (head, l < 3) or l - 3 (tail, 3 <= l < 6); for shift s
+  // it owns column col0 + 1 + l - s (head, kept when l + 1 >= s) or
+  // col0 + 256 - s + e (tail, kept when e < s), at packed offset
+  // A0 + 1 + l or A0 + 253 + l
+  const bool head = l < 3;
+  const int e = head ? l : l - 3;
+  float edge[3][D];
 #pragma unroll
-  for (int o = 0; o < 3; ++o)
+  for (int s = 1; s <= 3; ++s) {
+    const bool ok = l < 6 && (head ? l + 1 >= s : e < s);
+    const int64_t c = head ? col0 + 1 + l - s : col0 + 256 - s + e;
 #pragma unroll
-    for (int k = 0; k < D; ++k) tail[o][k] = a.X[(col0 + 253 + o) * a.ldx + k];
+    for (int k = 0; k < D; ++k) edge[s - 1][k] = ok ? a.X[c * a.ldx + k] : 0.0f;
+  }
+  const int eoff = head ? 1 + l : 253 + l;
   constexpr int PASSES = TS / 4;
 #pragma unroll 4
   for (int ps = 0; ps < PASSES; ++ps) {
@@ -59,52 +73,38 @@ __device__ __forceinline__ void packed_vec_rows(const EdmArgs &a, const float *x
     float xi[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) xi[k] = xs[r * D + k];
-    const uint64_t first = tri64(i) + (uint64_t)col0;
+    const uint64_t first = out_index<LAYOUT>(i, (uint64_t)col0, 0);
     const int sh = (int)(first & 3);
     const uint64_t A0 = first - (uint64_t)sh;
-    float v0, v1, v2, v3;
+    float v0, v1, v2, v3, ve;
     switch (sh) {
       case 0:
         v0 = pair_dist<D>(xi, win[3]); v1 = pair_dist<D>(xi, win[4]);
         v2 = pair_dist<D>(xi, win[5]); v3 = pair_dist<D>(xi, win[6]);
+        ve = 0.0f;
         break;
       case 1:
         v0 = pair_dist<D>(xi, win[2]); v1 = pair_dist<D>(xi, win[3]);
         v2 = pair_dist<D>(xi, win[4]); v3 = pair_dist<D>(xi, win[5]);
+        ve = pair_dist<D>(xi, edge[0]);
         break;
       case 2:
         v0 = pair_dist<D>(xi, win[1]); v1 = pair_dist<D>(xi, win[2]);
         v2 = pair_dist<D>(xi, win[3]); v3 = pair_dist<D>(xi, win[4]);
+        ve = pair_dist<D>(xi, edge[1]);
         break;
       default:
         v0 = pair_dist<D>(xi, win[0]); v1 = pair_dist<D>(xi, win[1]);
         v2 = pair_dist<D>(xi, win[2]); v3 = pair_dist<D>(xi, win[3]);
+        ve = pair_dist<D>(xi, edge[2]);
         break;
     }
     if (l > 0 || sh == 0) {
       f4 v = {v0, v1, v2, v3};
       __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(out + A0 + 4 * l));
-    } else {
-      // head: chunk positions sh..3 hold columns col0 .. col0 + 3 - sh
-      if (sh <= 1) __builtin_nontemporal_store(v1, out + A0 + 1);
-      if (sh <= 2) __builtin_nontemporal_store(v2, out + A0 + 2);
-      __builtin_nontemporal_store(v3, out + A0 + 3);
-      // tail: columns col0 + 256 - sh .. col0 + 255 (tail[o] is column
-      // col0 + 253 + o)
-      const float t0 = pair_dist<D>(xi, tail[0]);
-      const float t1 = pair_dist<D>(xi, tail[1]);
-      const float t2 = pair_dist<D>(xi, tail[2]);
-      if (sh == 1) {
-        __builtin_nontemporal_store(t2, out + A0 + 256);
-      } else if (sh == 2) {
-        __builtin_nontemporal_store(t1, out + A0 + 256);
-        __builtin_nontemporal_store(t2, out + A0 + 257);
-      } else {
-        __builtin_nontemporal_store(t0, out + A0 + 256);
-        __builtin_nontemporal_store(t1, out + A0 + 257);
-        __builtin_nontemporal_store(t2, out + A0 + 258);
-      }
     }
+    if (sh != 0 && l < 6 && (head ? l + 1 >= sh : e < sh))
+      __builtin_nontemporal_store(ve, out + A0 + eoff);
   }
 }
 
@@ -149,9 +149,9 @@ __global__ __launch_bounds__(256) void edm_tile_kernel(EdmArgs a, uint32_t lam0)
 
   float *__restrict__ out = a.D;
   const bool interior = (J < I) && (row0 + TS <= N);
-  if constexpr (VEC && LAYOUT == kLayoutPacked) {
+  if constexpr (VEC && LAYOUT != kLayoutFull) {
     if (interior) {
-      packed_vec_rows<TS, D>(a, xs, row0, col0, lr, out);
+      packed_vec_rows<TS, D, LAYOUT>(a, xs, row0, col0, lr, out);
       return;
     }
   }
@@ -175,7 +175,8 @@ __global__ __launch_bounds__(256) void edm_tile_kernel(EdmArgs a, uint32_t lam0)
       }
     }
   } else {
-    // diagonal or edge tile: keep cells with j <= i < N (j < N follows)
+    // diagonal or edge tile: keep cells with j <= i < N (j < i for the
+    // layout without the diagonal; j < N follows)
     for (int ps = 0; ps < PASSES; ++ps) {
       const int r = lr + ps * RPP;
       const int64_t i = row0 + r;
@@ -186,7 +187,78 @@ __global__ __launch_bounds__(256) void edm_tile_kernel(EdmArgs a, uint32_t lam0)
       const uint64_t idx = out_index<LAYOUT>(i, col0 + lc, a.ldd);
 #pragma unroll
       for (int q = 0; q < V; ++q) {
-        if (col0 + lc + q <= i) __builtin_nontemporal_store(pair_dist<D>(xi, xj[q]), out + idx + q);
+        if (in_triangle<LAYOUT>(i, col0 + lc + q))
+          __builtin_nontemporal_store(pair_dist<D>(xi, xj[q]), out + idx + q);
+      }
+    }
+  }
+}
+
+// Full layout, TS = 256, no LDS: a wave owns whole tile rows (64 lanes x 4
+// columns), so the row point is uniform across the wave and is read through
+// the scalar cache (X and D are separate restrict arguments), and there is
+// no work-group barrier before the first store.
+template <int D, bool BB>
+__global__ __launch_bounds__(256) void edm_tile256_kernel(const float *__restrict__ X, int64_t N,
+                                                          int64_t ldx, float *__restrict__ out,
+                                                          int64_t ldd, uint32_t lam0) {
+  constexpr int TS = 256;
+  uint32_t I, J;
+  if constexpr (BB) {
+    J = blockIdx.x;
+    I = blockIdx.y;
+    if (J > I) return;
+  } else {
+    g_lambda(lam0 + blockIdx.x, I, J);
+  }
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lc = (threadIdx.x & 63) * 4;
+  const int64_t row0 = (int64_t)I * TS;
+  const int64_t col0 = (int64_t)J * TS;
+  float xj[4][D];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t p = col0 + lc + q;
+#pragma unroll
+    for (int k = 0; k < D; ++k) xj[q][k] = p < N ? X[p * ldx + k] : 0.0f;
+  }
+  const bool interior = (J < I) && (row0 + TS <= N);
+  if (interior) {
+#pragma unroll 8
+    for (int ps = 0; ps < TS / 4; ++ps) {
+      const int64_t i = row0 + w + 4 * ps;
+      float xi[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) xi[k] = X[i * ldx + k];
+      f4 v;
+      v.x = pair_dist<D>(xi, xj[0]);
+      v.y = pair_dist<D>(xi, xj[1]);
+      v.z = pair_dist<D>(xi, xj[2]);
+      v.w = pair_dist<D>(xi, xj[3]);
+      __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(out + i * ldd + col0 + lc));
+    }
+  } else {
+    // diagonal or edge tile: rows below N, cells with j <= i; the row count
+    // is computed up front so the row index stays uniform (scalar loads)
+    const int64_t left = N - row0 - w;
+    const int rows = left <= 0 ? 0 : (int)((left + 3) / 4 < TS / 4 ? (left + 3) / 4 : TS / 4);
+    for (int ps = 0; ps < rows; ++ps) {
+      const int64_t i = row0 + w + 4 * ps;
+      float xi[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) xi[k] = X[i * ldx + k];
+      float v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = pair_dist<D>(xi, xj[q]);
+      const int64_t c = col0 + lc;
+      float *o = out + i * ldd + c;
+      if (c + 3 <= i) {
+        f4 v4 = {v[0], v[1], v[2], v[3]};
+        __builtin_nontemporal_store(v4, reinterpret_cast<f4 *>(o));
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (c + q <= i) __builtin_nontemporal_store(v[q], o + q);
       }
     }
   }
@@ -194,6 +266,25 @@ __global__ __launch_bounds__(256) void edm_tile_kernel(EdmArgs a, uint32_t lam0)
 
 template <int TS, int D, int LAYOUT, bool VEC>
 static hipError_t launch_tiled_t(bool bb, const EdmArgs &a) {
+  if constexpr (TS == 256 && LAYOUT == kLayoutFull && VEC) {
+    // the scalar-cache variant for the aligned full layout
+    const uint64_t nb = (uint64_t)((a.N + TS - 1) / TS);
+    if (bb) {
+      hipLaunchKernelGGL((edm_tile256_kernel<D, true>), dim3((uint32_t)nb, (uint32_t)nb), dim3(256), 0,
+                         a.stream, a.X, a.N, a.ldx, a.D, a.ldd, 0u);
+      return hipGetLastError();
+    }
+    const uint64_t T = nb * (nb + 1) / 2;
+    const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
+    for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
+      const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
+      hipLaunchKernelGGL((edm_tile256_kernel<D, false>), dim3((uint32_t)c), dim3(256), 0, a.stream,
+                         a.X, a.N, a.ldx, a.D, a.ldd, (uint32_t)l0);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   const uint64_t nb = (uint64_t)((a.N + TS - 1) / TS);
   if (bb) {
     hipLaunchKernelGGL((edm_tile_kernel<TS, D, LAYOUT, VEC, true>), dim3((uint32_t)nb, (uint32_t)nb),
@@ -212,15 +303,19 @@ static hipError_t launch_tiled_t(bool bb, const EdmArgs &a) {
   return hipSuccess;
 }
 
+template <int TS, int D, int LAYOUT>
+static hipError_t launch_tiled_packed(bool bb, const EdmArgs &a) {
+  if constexpr (TS == 256) {
+    if ((reinterpret_cast<uintptr_t>(a.D) & 15) == 0)
+      return launch_tiled_t<TS, D, LAYOUT, true>(bb, a);
+  }
+  return launch_tiled_t<TS, D, LAYOUT, false>(bb, a);
+}
+
 template <int TS, int D>
 static hipError_t launch_tiled_d(bool bb, const EdmArgs &a) {
-  if (a.layout == kLayoutPacked) {
-    if constexpr (TS == 256) {
-      if ((reinterpret_cast<uintptr_t>(a.D) & 15) == 0)
-        return launch_tiled_t<TS, D, kLayoutPacked, true>(bb, a);
-    }
-    return launch_tiled_t<TS, D, kLayoutPacked, false>(bb, a);
-  }
+  if (a.layout == kLayoutPacked) return launch_tiled_packed<TS, D, kLayoutPacked>(bb, a);
+  if (a.layout == kLayoutStrict) return launch_tiled_packed<TS, D, kLayoutStrict>(bb, a);
   const bool aligned = (a.ldd % 4 == 0) && ((reinterpret_cast<uintptr_t>(a.D) & 15) == 0);
   return aligned ? launch_tiled_t<TS, D, kLayoutFull, true>(bb, a)
                  : launch_tiled_t<TS, D, kLayoutFull, false>(bb, a);

@@ -24,12 +24,12 @@ LIB_PATH = os.path.join(_HERE, "libtdmap.so")
 # enums (include/tdmap.h)
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = range(5)
 LTM, BB, UTM, RB, REC = range(5)
-FULL, PACKED = 0, 1
+FULL, PACKED, PACKED_STRICT = 0, 1, 2
 FP32, BF16_GRAM = 0, 1
 OP_EDM, OP_BACKWARD, OP_BATCHED = 0, 1, 2
 
 STRATEGIES = {"ltm": LTM, "bb": BB, "utm": UTM, "rb": RB, "rec": REC}
-LAYOUTS = {"full": FULL, "packed": PACKED}
+LAYOUTS = {"full": FULL, "packed": PACKED, "strict": PACKED_STRICT}
 PRECISIONS = {"fp32": FP32, "bf16_gram": BF16_GRAM}
 
 
@@ -59,6 +59,7 @@ def _load() -> ctypes.CDLL:
                              ctypes.c_void_p, ctypes.c_size_t)
     sig = {
         "tdmap_map_blocks": ([u64, u64, vp, vp], ctypes.c_int),
+        "tdmap_map_blocks_nodiag": ([u64, u64, vp, vp], ctypes.c_int),
         "tdmap_edm": ([vp, i64, i32, i64, vp, i64, i32, i32, i32, i32, vp, sz, vp],
                       ctypes.c_int),
         "tdmap_edm_backward": ([vp, i64, i32, i64, vp, i64, i32, vp, i32, i32, vp, sz, vp],
@@ -83,7 +84,7 @@ def _load() -> ctypes.CDLL:
 
 
 EXPORTED = (
-    "tdmap_map_blocks", "tdmap_edm", "tdmap_edm_backward", "tdmap_edm_batched",
+    "tdmap_map_blocks", "tdmap_map_blocks_nodiag", "tdmap_edm", "tdmap_edm_backward", "tdmap_edm_batched",
     "tdmap_workspace_size", "tdmap_waste_counts", "tdmap_count_waste",
     "tdmap_map_blocks_variant", "tdmap_dummy",
     "tdmap_tuned_rho", "tdmap_autotune_reset", "tdmap_status_string",
@@ -102,6 +103,11 @@ def _check(status: int, where: str) -> None:
 
 def tdmap_map_blocks(lambda0: int, count: int, ij: int, stream: int) -> None:
     _check(_load().tdmap_map_blocks(lambda0, count, ij, stream), "tdmap_map_blocks")
+
+
+def tdmap_map_blocks_nodiag(lambda0: int, count: int, ij: int, stream: int) -> None:
+    _check(_load().tdmap_map_blocks_nodiag(lambda0, count, ij, stream),
+           "tdmap_map_blocks_nodiag")
 
 
 def tdmap_edm(X: int, N: int, d: int, ldx: int, D: int, ldd: int, layout: int,
@@ -194,6 +200,10 @@ def packed_size(N: int) -> int:
     return N * (N + 1) // 2
 
 
+def strict_size(N: int) -> int:
+    return N * (N - 1) // 2 if N > 0 else 0
+
+
 def map_blocks(lambda0: int, count: int, out=None):
     """g(lambda) for lambda0 .. lambda0+count-1 as a (count, 2) int32 tensor
     holding the uint32 (i, j) bits."""
@@ -201,6 +211,15 @@ def map_blocks(lambda0: int, count: int, out=None):
     if out is None:
         out = torch.empty((count, 2), dtype=torch.int32, device="cuda")
     tdmap_map_blocks(lambda0, count, out.data_ptr() if count else 0, _stream())
+    return out
+
+
+def map_blocks_nodiag(lambda0: int, count: int, out=None):
+    """The map without the diagonal for lambda0 .. lambda0+count-1."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((count, 2), dtype=torch.int32, device="cuda")
+    tdmap_map_blocks_nodiag(lambda0, count, out.data_ptr() if count else 0, _stream())
     return out
 
 
@@ -233,6 +252,8 @@ def edm(X, layout: str = "full", strategy: str = "ltm", rho: int = 0,
     if out is None:
         if lay == FULL:
             out = torch.empty((N, N), dtype=torch.float32, device=X.device)
+        elif lay == PACKED_STRICT:
+            out = torch.empty(strict_size(N), dtype=torch.float32, device=X.device)
         else:
             out = torch.empty(packed_size(N), dtype=torch.float32, device=X.device)
     if ldd is None:

@@ -74,6 +74,25 @@ def test_validation_rejects_before_launch(lib):
     assert L.tdmap_dummy(tdmap.BB, 1, 100, 16, 0, 8, None) == tdmap.ERR_INVALID
     assert L.tdmap_dummy(0, 0, 100, 64, 0, 8, None) == tdmap.ERR_UNSUPPORTED
     assert L.tdmap_dummy(0, 0, 100, 16, 0, None, None) == tdmap.ERR_INVALID
+    # the layout without the diagonal: FP32 tiles or the sweep, LTM / BB only
+    S = tdmap.PACKED_STRICT
+    for strat, rho in [(tdmap.LTM, 16), (tdmap.UTM, 16), (tdmap.RB, 8), (tdmap.REC, 32),
+                       (tdmap.BB, 1), (tdmap.UTM, 64)]:
+        assert L.tdmap_edm(8, 10, 3, 3, 16, 0, S, strat, rho, 0, None, 0, None) \
+            == tdmap.ERR_UNSUPPORTED, (strat, rho)
+    assert L.tdmap_edm(8, 10, 3, 3, 16, 0, S, 0, 0, tdmap.BF16_GRAM, 8, 1 << 20, None) \
+        == tdmap.ERR_UNSUPPORTED
+    # the sweep needs a 16-byte aligned output
+    assert L.tdmap_edm(8, 10, 3, 3, 20, 0, S, 0, 1, 0, None, 0, None) == tdmap.ERR_UNSUPPORTED
+    # NULL output: invalid unless N = 1 (no cell); a layout past the last one
+    assert L.tdmap_edm(8, 10, 3, 3, None, 0, S, 0, 64, 0, None, 0, None) == tdmap.ERR_INVALID
+    assert L.tdmap_edm(8, 10, 3, 3, 16, 0, 3, 0, 64, 0, None, 0, None) == tdmap.ERR_INVALID
+    assert L.tdmap_edm_backward(8, 10, 3, 3, None, 0, S, 8, 64, 0, None, 0, None) \
+        == tdmap.ERR_INVALID
+    # the no-diagonal map validates like the map
+    assert L.tdmap_map_blocks_nodiag(0, 10, None, None) == tdmap.ERR_INVALID
+    assert L.tdmap_map_blocks_nodiag((1 << 32) - 5, 6, 8, None) == tdmap.ERR_UNSUPPORTED
+    assert L.tdmap_map_blocks_nodiag(5, 0, None, None) == tdmap.OK
     # the instrumented count needs a paper-style rho
     assert L.tdmap_count_waste(0, 100, 64, 8, None) == tdmap.ERR_UNSUPPORTED
     assert L.tdmap_count_waste(0, 100, 16, None, None) == tdmap.ERR_INVALID

@@ -66,6 +66,23 @@ def test_edm_one_feature_is_absolute_difference(impl):
                                       np.abs(x[i] - x[: i + 1]))
 
 
+@pytest.mark.parametrize("N,d", [(0, 3), (1, 3), (2, 1), (3, 2), (37, 3), (130, 4)])
+def test_edm_strict_matches_scipy_pdist(N, d):
+    # the layout without the diagonal is the strictly lower triangle of the
+    # distance matrix in row-major order, which numpy's tril_indices(N, -1)
+    # enumerates; the map of Eq. (10) names the same cell for every index
+    from oracle import maps
+    X = synth.uniform_points(N, d, seed=21 + N + d)
+    S = squareform(pdist(X.astype(np.float64))) if N > 1 else np.zeros((N, N))
+    ref = S[np.tril_indices(N, -1)]
+    got = edm.edm64_strict(X)
+    assert got.shape == (N * (N - 1) // 2 if N else 0,)
+    np.testing.assert_allclose(got, ref, rtol=1e-15, atol=0)
+    for lam in range(got.size):
+        i, j = maps.g_oracle_nodiag(lam)
+        assert got[lam] == S[i, j]
+
+
 def test_edm_rows_and_full_agree_with_packed():
     X = synth.uniform_points(150, 3, seed=9)
     P = edm.edm64_packed(X)
