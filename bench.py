@@ -236,11 +236,13 @@ def first_map_failure(torch, tdmap, variant, chunk=1 << 27):
                 return 0
         else:
             pi, pj = prev
-            ok0 = (int(i[0]) == pi and int(j[0]) == pj + 1) or \
+            ok0 = (int(i[0]) == pi and int(j[0]) == pj + 1 <= pi) or \
                   (int(i[0]) == pi + 1 and int(j[0]) == 0 and pj == pi)
             if not ok0:
                 return lam0
-        ok = ((i[1:] == i[:-1]) & (j[1:] == j[:-1] + 1)) | \
+        # the next cell of the row (still on or below the diagonal), or the
+        # first cell of the next row
+        ok = ((i[1:] == i[:-1]) & (j[1:] == j[:-1] + 1) & (j[1:] <= i[1:])) | \
              ((i[1:] == i[:-1] + 1) & (j[1:] == 0) & (j[:-1] == i[:-1]))
         bad = torch.nonzero(~ok)
         if bad.numel():
@@ -260,9 +262,7 @@ def row_mapcost(torch, tdmap, synth):
         row = {}
         for s in ("ltm", "bb", "utm", "rb", "rec"):
             row[s] = _med_ms(lambda s=s: tdmap.dummy(s, N, rho, sink=sink), 10) * 1e3
-        for s in list(row):
-            row[s] = {"us": row[s], "I_vs_bb": row["bb"] / row[s]}
-        res[f"rho{rho}"] = row
+        res[f"rho{rho}"] = {s: {"us": t, "I_vs_bb": row["bb"] / t} for s, t in row.items()}
     var = {}
     t_bb = res["rho16"]["bb"]["us"]
     for v, name in ((0, "ltm_fixup"), (1, "ltm_x_sqrtf"), (2, "ltm_r_rsq_eps")):
@@ -354,10 +354,14 @@ def main():
 
     achieved = bytes_alg / (kern_ms * 1e-3) / 1e9
     traffic = stored_traffic()
+    kname = (f"edm_tile256_kernel<{d}, false>" if ts_ltm == 256
+             else f"edm_tile_kernel<{ts_ltm}, {d}, 0, true, false>")
+    if traffic and not traffic["kernel"].startswith(kname):
+        traffic = None  # the counters were taken on another tile kernel
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic["bytes_per_launch"] if traffic else None,
-                "kernel": "edm_tile_kernel (LTM, full layout)",
+                "kernel": kname + " (LTM, full layout)",
                 "algorithmic_bytes_per_launch": bytes_alg}
 
     result = {
