@@ -17,9 +17,26 @@ namespace tdmap {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+// Sum over the 64 lanes of a wave with DPP lane moves (plain VALU adds, no
+// LDS crossbar traffic): swaps within quads, mirrors within 8 and 16 lanes
+// leave every lane of a 16-lane row holding the row's sum; two row
+// broadcasts then accumulate rows 0..3 into row 3.  The total is valid in
+// lane 63 (kSumLane).
+constexpr int kSumLane = 63;
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xF, false));
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_move<0x140, 0xF>(v);  // row_mirror
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
   return v;
 }
 
@@ -106,7 +123,7 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
         }
 #pragma unroll
         for (int k = 0; k < D; ++k) rs[k] = wave_sum(rs[k]);
-        if (l == 0) {
+        if (l == kSumLane) {
 #pragma unroll
           for (int k = 0; k < D; ++k) rowp[r * D + k] = rs[k];
         }
@@ -147,7 +164,7 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
       }
 #pragma unroll
       for (int k = 0; k < D; ++k) rs[k] = wave_sum(rs[k]);
-      if (l == 0) {
+      if (l == kSumLane) {
 #pragma unroll
         for (int k = 0; k < D; ++k) rowp[r * D + k] = rs[k];
       }
@@ -295,7 +312,7 @@ __global__ __launch_bounds__(256) void edm_bwd_tile256(BwdArgs a, uint32_t lam0)
       }
 #pragma unroll
       for (int k = 0; k < D; ++k) rs[k] = wave_sum(rs[k]);
-      if (l == 0) {
+      if (l == kSumLane) {
 #pragma unroll
         for (int k = 0; k < D; ++k) rowp[r * D + k] = rs[k];
       }
@@ -322,9 +339,11 @@ __global__ __launch_bounds__(256) void edm_bwd_tile256(BwdArgs a, uint32_t lam0)
   }
 }
 
-// Deterministic second pass: point p in block B = p / TS collects the row
-// partials of tiles (B, 0..B) and the column partials of tiles (B..nb-1, B),
-// in that order.
+// Deterministic second pass: point p in block B = p / TS collects nb + 1
+// partials: entry t <= B is the row partial of tile (B, t), entry t > B the
+// column partial of tile (B + t - B - 1, B).  Eight accumulators take every
+// eighth entry (eight loads in flight per thread) and are added in a fixed
+// tree, so the result does not depend on timing.
 template <int TS, int D>
 __global__ __launch_bounds__(TS * D) void edm_bwd_reduce(const float *__restrict__ ws,
                                                          float *__restrict__ dX, int64_t N,
@@ -334,11 +353,24 @@ __global__ __launch_bounds__(TS * D) void edm_bwd_reduce(const float *__restrict
   const int64_t p = (int64_t)B * TS + e / D;
   if (p >= N) return;
   constexpr int STRIDE = 2 * TS * D;
-  float acc = 0.0f;
   const uint64_t tb = tri64(B);
-  for (uint32_t j = 0; j <= B; ++j) acc += ws[(tb + j) * STRIDE + e];
-  for (uint32_t i = B; i < nb; ++i) acc += ws[(tri64(i) + B) * STRIDE + TS * D + e];
-  dX[(uint64_t)B * TS * D + e] = acc;
+  auto entry = [&](uint32_t t) -> float {
+    return t <= B ? ws[(tb + t) * STRIDE + e]
+                  : ws[(tri64(t - 1) + B) * STRIDE + TS * D + e];
+  };
+  const uint32_t cnt = nb + 1;
+  float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  uint32_t t = 0;
+  for (; t + 8 <= cnt; t += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = entry(t + u);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += v[u];
+  }
+  for (; t < cnt; ++t) acc[0] += entry(t);
+  dX[(uint64_t)B * TS * D + e] =
+      ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }
 
 template <int TS, int D, int LAYOUT, bool DET>
