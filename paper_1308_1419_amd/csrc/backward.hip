@@ -4,12 +4,11 @@
 // For a cell (i, j), j < i, with g = dL/dD_ij and diff = x_i - x_j:
 //   c = g / ||diff|| = g * rsq(||diff||^2)   (0 when ||diff|| = 0)
 //   dX_i += c * diff,   dX_j -= c * diff.
-// A 256-thread work-group owns a TS x TS tile (I, J) = g(lambda).  Lanes map
-// to columns (TS / 64 per lane) so every dD row segment is read with
-// coalesced 4-byte loads; waves split the rows.  Column sums stay in
-// registers; each row sum is reduced across the wave.  Per-tile partial
-// sums then either go to a workspace (deterministic: a second kernel adds
-// them in a fixed order) or are added to dX with atomics.
+// A 256-thread work-group owns a TS x TS tile (I, J) = g(lambda).  Column
+// sums stay in registers; row sums are reduced across lanes with DPP moves.
+// Per-tile partial sums then either go to a workspace (deterministic: a
+// second kernel adds them in a fixed order) or are added to dX with
+// atomics.
 #include "device.h"
 #include "kernels.h"
 
@@ -40,153 +39,181 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Sum over the 16 lanes of a DPP row (lanes 16r .. 16r + 15); every lane of
+// the row receives the sum.
+__device__ __forceinline__ float row16_sum(float v) {
+  v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_move<0x140, 0xF>(v);  // row_mirror
+  return v;
+}
+
+// The steps of one wave's tile quarter (rows rq0 .. rq0 + H - 1 of the tile,
+// the columns of cbase): dD of step s holds rows rq0 + 16 s + 4 rg + p and
+// columns cbase + 16 q; cells outside the strict lower triangle or past N
+// read 0 (edge and diagonal tiles only).  Row sums go to rowp, column sums
+// accumulate in cacc.
+template <int TS, int D, int LAYOUT, bool INTERIOR>
+__device__ __forceinline__ void bwd_quarter_steps(const BwdArgs &a, const float *xs, float *rowp,
+                                                  const float (&xj)[TS / 32][D],
+                                                  const bool (&jok)[TS / 32],
+                                                  float (&cacc)[TS / 32][D], int64_t row0,
+                                                  int64_t cbase, int rq0, int rg, int cg,
+                                                  bool diag) {
+  constexpr int Q = TS / 32;
+  constexpr int STEPS = TS / 32;
+  const int64_t N = a.N;
+  auto load_step = [&](int s, float (&g)[4][Q]) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int64_t i = row0 + rq0 + 16 * s + 4 * rg + p;
+      const uint64_t base = out_index<LAYOUT>((uint64_t)i, (uint64_t)cbase, a.ldd);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if constexpr (INTERIOR) {
+          g[p][q] = a.dD[base + 16 * q];
+        } else {
+          const int64_t j = cbase + 16 * q;
+          const bool ok = i < N && jok[q] && (!diag || j < i);
+          g[p][q] = ok ? a.dD[base + 16 * q] : 0.0f;
+        }
+      }
+    }
+  };
+#pragma unroll 1
+  for (int s = 0; s < STEPS; ++s) {
+    float g[4][Q];
+    load_step(s, g);
+    const int rl = rq0 + 16 * s + 4 * rg;  // tile-local row of p = 0
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      float xi[D], rs[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        xi[k] = xs[(rl + p) * D + k];
+        rs[k] = 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        float diff[D];
+        float s2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          diff[k] = xi[k] - xj[q][k];
+          s2 = __builtin_fmaf(diff[k], diff[k], s2);
+        }
+        // g is 0 for every cell outside the strict lower triangle
+        const float cc = s2 > 0.0f ? g[p][q] * __builtin_amdgcn_rsqf(s2) : 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          rs[k] = __builtin_fmaf(cc, diff[k], rs[k]);
+          cacc[q][k] = __builtin_fmaf(-cc, diff[k], cacc[q][k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) rs[k] = row16_sum(rs[k]);
+      if (cg == 15) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) rowp[(rl + p) * D + k] = rs[k];
+      }
+    }
+  }
+}
+
+// TS = 64 or 128.  The four waves split the tile into 2 x 2 quarters of
+// H = TS/2 rows and columns; wave w takes row half w >> 1 and column half
+// w & 1.  Inside a wave, lane l = 16 rg + cg owns columns cg + 16q
+// (q < Q = H/16) of its column half, so one load instruction reads 64
+// consecutive bytes of four rows, and rows 4 rg .. 4 rg + 3 of each 16-row
+// step.  A lane thus works on a 4 x Q block of cells per step: the row sums
+// of its four rows are reduced over only the 16 lanes of its DPP row
+// (full-rate moves, no broadcasts), and the column sums stay in registers
+// for the whole tile and are reduced over the four row groups once at the
+// end.  A step's 4 x Q loads are issued together before its arithmetic; the
+// next step's are not prefetched, which keeps the register count at four
+// waves per SIMD (measured faster than prefetching at three).
 template <int TS, int D, int LAYOUT, bool DET>
 __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
+  constexpr int H = TS / 2;
+  constexpr int Q = H / 16;      // columns per lane
   const uint32_t lam = lam0 + blockIdx.x;
   uint32_t I, J;
   g_lambda(lam, I, J);
-  constexpr int CPL = TS / 64;  // columns per lane
-  constexpr int RPW = TS / 4;   // rows per wave
   const int t = threadIdx.x;
   const int w = t >> 6;
   const int l = t & 63;
+  const int ch = w & 1;
+  const int rh = w >> 1;
+  const int rg = l >> 4;
+  const int cg = l & 15;
   const int64_t N = a.N;
   const int64_t row0 = (int64_t)I * TS;
   const int64_t col0 = (int64_t)J * TS;
+  const int64_t cbase = col0 + H * ch + cg;  // column of q = 0
 
   __shared__ float xs[TS * D];
-  __shared__ float rowp[TS * D];
-  __shared__ float colp[4][TS * D];
-
+  __shared__ float rowp[2][TS * D];  // by column half
+  __shared__ float colp[2][TS * D];  // by row half
   for (int e = t; e < TS * D; e += 256) {
     const int r = e / D;
     const int k = e - r * D;
     const int64_t p = row0 + r;
     xs[e] = p < N ? a.X[p * a.ldx + k] : 0.0f;
   }
-  float xj[CPL][D];
-  bool jok[CPL];
+  float xj[Q][D];
+  bool jok[Q];
 #pragma unroll
-  for (int c = 0; c < CPL; ++c) {
-    const int64_t j = col0 + l + 64 * c;
-    jok[c] = j < N;
+  for (int q = 0; q < Q; ++q) {
+    const int64_t j = cbase + 16 * q;
+    jok[q] = j < N;
 #pragma unroll
-    for (int k = 0; k < D; ++k) xj[c][k] = jok[c] ? a.X[j * a.ldx + k] : 0.0f;
+    for (int k = 0; k < D; ++k) xj[q][k] = jok[q] ? a.X[j * a.ldx + k] : 0.0f;
   }
-  float cacc[CPL][D];
+  float cacc[Q][D];
 #pragma unroll
-  for (int c = 0; c < CPL; ++c)
+  for (int q = 0; q < Q; ++q)
 #pragma unroll
-    for (int k = 0; k < D; ++k) cacc[c][k] = 0.0f;
-  __syncthreads();
+    for (int k = 0; k < D; ++k) cacc[q][k] = 0.0f;
 
+  __syncthreads();
   const bool diag = I == J;
-  const bool interior = (J < I) && (row0 + TS <= N);
-  if (interior) {
-    // every cell of the tile is a live j < i cell: the dD loads are
-    // unconditional and issued four rows at a time
-    constexpr int RB = 4;
-    for (int rb = 0; rb < RPW; rb += RB) {
-      float g[RB][CPL];
+  if ((J < I) && (row0 + TS <= N))
+    bwd_quarter_steps<TS, D, LAYOUT, true>(a, xs, rowp[ch], xj, jok, cacc, row0, cbase, H * rh, rg,
+                                            cg, false);
+  else
+    bwd_quarter_steps<TS, D, LAYOUT, false>(a, xs, rowp[ch], xj, jok, cacc, row0, cbase, H * rh,
+                                             rg, cg, diag);
+  // column sums over the four row groups (lanes cg, cg + 16, cg + 32, cg + 48)
 #pragma unroll
-      for (int q = 0; q < RB; ++q) {
-        const int64_t i = row0 + (rb + q) * 4 + w;
-        const uint64_t base = out_index<LAYOUT>((uint64_t)i, (uint64_t)col0, a.ldd);
+  for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) g[q][c] = a.dD[base + l + 64 * c];
-      }
-#pragma unroll
-      for (int q = 0; q < RB; ++q) {
-        const int r = (rb + q) * 4 + w;
-        float xi[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) xi[k] = xs[r * D + k];
-        float rs[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) rs[k] = 0.0f;
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-          float diff[D];
-          float s2 = 0.0f;
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            diff[k] = xi[k] - xj[c][k];
-            s2 = __builtin_fmaf(diff[k], diff[k], s2);
-          }
-          const float cc = s2 > 0.0f ? g[q][c] * __builtin_amdgcn_rsqf(s2) : 0.0f;
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            const float v = cc * diff[k];
-            rs[k] += v;
-            cacc[c][k] -= v;
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < D; ++k) rs[k] = wave_sum(rs[k]);
-        if (l == kSumLane) {
-#pragma unroll
-          for (int k = 0; k < D; ++k) rowp[r * D + k] = rs[k];
-        }
-      }
+    for (int k = 0; k < D; ++k) {
+      float v = cacc[q][k];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      cacc[q][k] = v;
     }
-  } else {
-    for (int rr = 0; rr < RPW; ++rr) {
-      const int r = rr * 4 + w;
-      const int64_t i = row0 + r;
-      float rs[D];
+  if (rg == 0) {
 #pragma unroll
-      for (int k = 0; k < D; ++k) rs[k] = 0.0f;
-      if (i < N) {
-        float xi[D];
+    for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int k = 0; k < D; ++k) xi[k] = xs[r * D + k];
-        const uint64_t base = out_index<LAYOUT>((uint64_t)i, (uint64_t)col0, a.ldd);
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-          const int64_t j = col0 + l + 64 * c;
-          const bool ok = jok[c] && (!diag || j < i);
-          const float g = ok ? a.dD[base + l + 64 * c] : 0.0f;
-          float diff[D];
-          float s2 = 0.0f;
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            diff[k] = xi[k] - xj[c][k];
-            s2 = __builtin_fmaf(diff[k], diff[k], s2);
-          }
-          const float cc = (ok && s2 > 0.0f) ? g * __builtin_amdgcn_rsqf(s2) : 0.0f;
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            const float v = cc * diff[k];
-            rs[k] += v;
-            cacc[c][k] -= v;
-          }
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < D; ++k) rs[k] = wave_sum(rs[k]);
-      if (l == kSumLane) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) rowp[r * D + k] = rs[k];
-      }
-    }
+      for (int k = 0; k < D; ++k) colp[rh][(H * ch + cg + 16 * q) * D + k] = cacc[q][k];
   }
-#pragma unroll
-  for (int c = 0; c < CPL; ++c)
-#pragma unroll
-    for (int k = 0; k < D; ++k) colp[w][(l + 64 * c) * D + k] = cacc[c][k];
   __syncthreads();
 
   for (int e = t; e < TS * D; e += 256) {
-    const float cs = ((colp[0][e] + colp[1][e]) + colp[2][e]) + colp[3][e];
+    const float rsum = rowp[0][e] + rowp[1][e];
+    const float csum = colp[0][e] + colp[1][e];
     if constexpr (DET) {
       float *dst = a.ws + (uint64_t)lam * 2 * TS * D;
-      dst[e] = rowp[e];
-      dst[TS * D + e] = cs;
+      dst[e] = rsum;
+      dst[TS * D + e] = csum;
     } else {
       const int r = e / D;
       const int k = e - r * D;
-      if (row0 + r < N) atomicAdd(&a.dX[(row0 + r) * D + k], rowp[e]);
-      if (col0 + r < N) atomicAdd(&a.dX[(col0 + r) * D + k], cs);
+      if (row0 + r < N) atomicAdd(&a.dX[(row0 + r) * D + k], rsum);
+      if (col0 + r < N) atomicAdd(&a.dX[(col0 + r) * D + k], csum);
     }
   }
 }

@@ -93,9 +93,23 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // go cell by cell.
 constexpr int kGramRows = 16;  // rows staged per step and wave
 
-__global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t lam0) {
+// (i(i+1)/2 + col0) mod 4 for the tile row rr of a 16-row step: the step's
+// first row is a multiple of 16 and col0 a multiple of 128, and
+// i(i+1)/2 mod 4 has period 8 in i.
+__device__ __forceinline__ int row_shift(int rr) {
+  const int m = rr & 7;
+  return ((m * (m + 1)) >> 1) & 3;
+}
+
+__global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t lam0, uint32_t nblk) {
+  // Work-groups are dispatched round-robin over the eight XCDs (block b on
+  // XCD b mod 8).  Each XCD is given one contiguous range of lambda, so the
+  // tiles an XCD runs back to back share their row block and sweep the
+  // column blocks in order, and the BF16 operands they read stay in that
+  // XCD's L2.
+  const uint32_t b = blockIdx.x, xcd = b & 7, per = nblk >> 3, extra = nblk & 7;
   uint32_t I, J;
-  g_lambda(lam0 + blockIdx.x, I, J);
+  g_lambda(lam0 + xcd * per + (xcd < extra ? xcd : extra) + (b >> 3), I, J);
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int lr = l & 31;
@@ -137,7 +151,10 @@ __global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t 
     }
   }
 
-  __shared__ float stage[4][kGramRows][kGramTile + 4];
+  // stage row rr holds column c at position c + sh(rr), where sh(rr) is the
+  // offset of the packed row past a 16-byte boundary; the stored chunks are
+  // then aligned 16-byte LDS reads without bank conflicts
+  __shared__ __align__(16) float stage[4][kGramRows][kGramTile + 4];
   float(*st)[kGramTile + 4] = stage[w];
   float *__restrict__ out = a.D;
   const int h = l & 31;
@@ -157,7 +174,7 @@ __global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t 
         const bool rec = G <= kGramTheta * sn;
         any |= rec;
         // a pair below the threshold is marked -1 and filled in below
-        st[rr][bj * 32 + lr] = rec ? -1.0f : __builtin_amdgcn_sqrtf(G);
+        st[rr][bj * 32 + lr + row_shift(rr)] = rec ? -1.0f : __builtin_amdgcn_sqrtf(G);
       }
     }
     if (any) {
@@ -167,10 +184,11 @@ __global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t 
 #pragma unroll
         for (int v = 8 * vh; v < 8 * vh + 8; ++v) {
           const int rr = (v >> 2) * 8 + (l >> 5) * 4 + (v & 3) - 16 * vh;
-          if (st[rr][bj * 32 + lr] < 0.0f) {
+          const int c = bj * 32 + lr + row_shift(rr);
+          if (st[rr][c] < 0.0f) {
             const int64_t i = rw + 16 * vh + rr;
             const int64_t j = col0 + bj * 32 + lr;
-            st[rr][bj * 32 + lr] = (i < N && j <= i) ? exact_dist(a.X, a.ldx, a.d, i, j) : 0.0f;
+            st[rr][c] = (i < N && j <= i) ? exact_dist(a.X, a.ldx, a.d, i, j) : 0.0f;
           }
         }
       }
@@ -184,8 +202,7 @@ __global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t 
         const uint64_t first = tri64((uint64_t)(rw + 16 * vh + r)) + (uint64_t)col0;
         const int sh = (int)(first & 3);
         if (h > 0 || sh == 0) {
-          const int c = 4 * h - sh;
-          f4 v4 = {st[r][c], st[r][c + 1], st[r][c + 2], st[r][c + 3]};
+          const f4 v4 = *reinterpret_cast<const f4 *>(&st[r][4 * h]);
           __builtin_nontemporal_store(v4, reinterpret_cast<f4 *>(out + first - sh + 4 * h));
         }
       }
@@ -199,7 +216,7 @@ __global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t 
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int c = q < 4 - sh ? q : kGramTile - 4 + q;
-            __builtin_nontemporal_store(st[l][c], out + first + c);
+            __builtin_nontemporal_store(st[l][c + sh], out + first + c);
           }
         }
       }
@@ -209,9 +226,10 @@ __global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t 
         const int64_t i = rw + 16 * vh + r;
         if (i >= N) continue;
         const uint64_t first = tri64((uint64_t)i) + (uint64_t)col0;
+        const int sh = (int)(first & 3);
         const int64_t jmax = (diag ? i : N - 1) - col0;
         for (int c = h; c < kGramTile; c += 32)
-          if (c <= jmax) __builtin_nontemporal_store(st[r][c], out + first + c);
+          if (c <= jmax) __builtin_nontemporal_store(st[r][c + sh], out + first + c);
       }
     }
   }
@@ -240,7 +258,8 @@ hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, 
   const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
   for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
     const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
-    hipLaunchKernelGGL(gram_tile_kernel, dim3((uint32_t)c), dim3(256), 0, stream, a, (uint32_t)l0);
+    hipLaunchKernelGGL(gram_tile_kernel, dim3((uint32_t)c), dim3(256), 0, stream, a, (uint32_t)l0,
+                       (uint32_t)c);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
