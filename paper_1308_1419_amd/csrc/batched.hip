@@ -15,7 +15,9 @@
 // Inside a tile every wave owns whole rows: the row index is uniform across
 // the wave, so the row point is read once through the scalar cache, and
 // each lane computes TS/64 columns and writes them with 4-byte stores
-// (packed rows start at arbitrary offsets).
+// (packed rows start at arbitrary offsets).  The stores are plain (cached):
+// the cache lines at both ends of a tile's row segment are shared with the
+// neighbouring tiles and are combined in L2.
 #include "device.h"
 #include "kernels.h"
 
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(256) void edm_batched_kernel(const float *__restric
         for (int k = 0; k < D; ++k) xi[k] = Xs[i * D + k];
         float *__restrict__ o = out + tri64((uint64_t)i) + col0 + l;
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) __builtin_nontemporal_store(pair_dist<D>(xi, xj[c]), o + 64 * c);
+        for (int c = 0; c < CPL; ++c) o[64 * c] = pair_dist<D>(xi, xj[c]);
       }
     } else {
       for (int rr = 0; rr < RPW; ++rr) {
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(256) void edm_batched_kernel(const float *__restric
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
           const int64_t j = col0 + l + 64 * c;
-          if (j <= i) __builtin_nontemporal_store(pair_dist<D>(xi, xj[c]), o + j);
+          if (j <= i) o[j] = pair_dist<D>(xi, xj[c]);
         }
       }
     }

@@ -216,7 +216,10 @@ __global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t 
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int c = q < 4 - sh ? q : kGramTile - 4 + q;
-            __builtin_nontemporal_store(st[l][c + sh], out + first + c);
+            // plain (cached) store: the neighbouring tile writes the rest
+            // of this 16-byte chunk, and the two halves then meet in L2
+            // instead of reaching HBM as two partial line writes
+            out[first + c] = st[l][c + sh];
           }
         }
       }

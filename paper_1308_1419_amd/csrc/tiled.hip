@@ -11,8 +11,8 @@
 //     16-byte store, so a wave writes TS/4-lane runs of 16 bytes: whole
 //     64-byte segments of a row.  Without VEC (packed rows start at any
 //     offset) a lane owns one column and a wave writes 256 contiguous bytes.
-// Stores are non-temporal: the output is written once and not re-read, so
-// there is no point keeping it in L2.
+// Full-layout stores are non-temporal (the output is written once and not
+// re-read); packed-layout stores are plain (see put below).
 //
 // LTM launches exactly n(n+1)/2 work-groups, tile (I, J) = g(lambda).  BB
 // launches n x n and returns at once above the diagonal (Sec. III-B), with
@@ -23,6 +23,20 @@
 namespace tdmap {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Output stores.  Full-layout rows are written whole by one tile each, so
+// they bypass the caches (non-temporal).  Packed rows start at arbitrary
+// offsets: the 16-byte chunks and cache lines at both ends of a tile's row
+// segment are shared with the neighbouring tiles, and plain (cached) stores
+// let those parts meet in L2 instead of reaching HBM as separate partial
+// line writes (measured faster at every tile size).
+template <int LAYOUT, typename T>
+__device__ __forceinline__ void put(T v, T *p) {
+  if constexpr (LAYOUT == kLayoutFull)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
 
 // Interior tile rows in the packed layout with 16-byte stores (TS = 256:
 // one row per wave and pass).  Packed row i starts at R(i) = i(i+1)/2 (or
@@ -101,10 +115,9 @@ __device__ __forceinline__ void packed_vec_rows(const EdmArgs &a, const float *x
     }
     if (l > 0 || sh == 0) {
       f4 v = {v0, v1, v2, v3};
-      __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(out + A0 + 4 * l));
+      put<LAYOUT>(v, reinterpret_cast<f4 *>(out + A0 + 4 * l));
     }
-    if (sh != 0 && l < 6 && (head ? l + 1 >= sh : e < sh))
-      __builtin_nontemporal_store(ve, out + A0 + eoff);
+    if (sh != 0 && l < 6 && (head ? l + 1 >= sh : e < sh)) put<LAYOUT>(ve, out + A0 + eoff);
   }
 }
 
@@ -169,9 +182,9 @@ __global__ __launch_bounds__(256) void edm_tile_kernel(EdmArgs a, uint32_t lam0)
         v.y = pair_dist<D>(xi, xj[1]);
         v.z = pair_dist<D>(xi, xj[2]);
         v.w = pair_dist<D>(xi, xj[3]);
-        __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(out + idx));
+        put<LAYOUT>(v, reinterpret_cast<f4 *>(out + idx));
       } else {
-        __builtin_nontemporal_store(pair_dist<D>(xi, xj[0]), out + idx);
+        put<LAYOUT>(pair_dist<D>(xi, xj[0]), out + idx);
       }
     }
   } else {
@@ -188,7 +201,7 @@ __global__ __launch_bounds__(256) void edm_tile_kernel(EdmArgs a, uint32_t lam0)
 #pragma unroll
       for (int q = 0; q < V; ++q) {
         if (in_triangle<LAYOUT>(i, col0 + lc + q))
-          __builtin_nontemporal_store(pair_dist<D>(xi, xj[q]), out + idx + q);
+          put<LAYOUT>(pair_dist<D>(xi, xj[q]), out + idx + q);
       }
     }
   }
