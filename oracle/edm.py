@@ -166,31 +166,48 @@ U32 = 2.0 ** -24   # unit roundoff of FP32 (round to nearest)
 U_BF16 = 2.0 ** -8  # unit roundoff of BF16 (8-bit significand)
 
 
-def gram_bound(norm_i, norm_j, D64, d: int):
+def gram_bound(norm_i, norm_j, D64, d: int, split: bool = False):
     """Largest |D_gpu - D| allowed for a pair that the Gram path did not
     recompute, given ||x_i||, ||x_j||, the FP64 distance D and the feature
-    count d (arrays broadcast).
+    count d (arrays broadcast).  u denotes the BF16 unit roundoff, u32 the
+    FP32 one.
 
-    Terms:
-    * BF16 rounding of the inputs: |x~ - x| <= u_bf16 |x| per coordinate, so
-      by the triangle inequality | ||x~-y~|| - ||x-y|| | <= u_bf16 (||x||+||y||).
+    Terms, BF16 inputs (split = False):
+    * BF16 rounding of the inputs: |x~ - x| <= u |x| per coordinate, so
+      by the triangle inequality | ||x~-y~|| - ||x-y|| | <= u (||x||+||y||).
     * FP32 accumulation of n~_i + n~_j - 2 x~.y~ with d-term sums (products
       of BF16 values are exact in FP32): |G - G_exact| <= E with
-      E = 2 (d + 4) u32 (||x||^2 + ||y||^2) (1 + u_bf16)^2, and the square
+      E = 2 (d + 4) u32 (||x||^2 + ||y||^2) (1 + u)^2, and the square
       root turns E into at most E / D_lower where D_lower is a lower bound of
       the BF16 distance (pairs above the threshold are far from 0).
     * the final square root and store: 2 ulp of D.
+
+    Split inputs (split = True: x = hi + lo with hi = bf16(x) and
+    lo = bf16(x - hi), the dot product taken as hi.hi' + hi.lo' + lo.hi'):
+    * x - hi is exact in FP32 and |x - hi| <= u |x|, so
+      |x - (hi + lo)| <= u |x - hi| <= u^2 |x|: the representation term
+      becomes u^2 (||x||+||y||);
+    * the dot product sums 3d exact products, and the dropped lo.lo' is at
+      most ||lo|| ||lo'|| <= u^2 (1 + u)^2 ||x|| ||y||:
+      E = 2 (3d + 4) u32 (||x||^2 + ||y||^2) (1 + u)^2
+          + 2 u^2 (1 + u)^2 ||x|| ||y||.
     """
     norm_i = np.asarray(norm_i, dtype=np.float64)
     norm_j = np.asarray(norm_j, dtype=np.float64)
     D64 = np.asarray(D64, dtype=np.float64)
-    bf = U_BF16 * (norm_i + norm_j)
-    E = 2.0 * (d + 4) * U32 * (norm_i ** 2 + norm_j ** 2) * (1 + U_BF16) ** 2
-    D_lower = np.maximum(D64 - bf, 0.0)
+    u = U_BF16
+    if split:
+        rep = u * u * (norm_i + norm_j)
+        E = (2.0 * (3 * d + 4) * U32 * (norm_i ** 2 + norm_j ** 2) * (1 + u) ** 2
+             + 2.0 * u * u * (1 + u) ** 2 * norm_i * norm_j)
+    else:
+        rep = u * (norm_i + norm_j)
+        E = 2.0 * (d + 4) * U32 * (norm_i ** 2 + norm_j ** 2) * (1 + u) ** 2
+    D_lower = np.maximum(D64 - rep, 0.0)
     acc = np.where(D_lower > 0, E / np.where(D_lower > 0, D_lower, 1.0),
                    np.sqrt(E))
     acc = np.minimum(acc, np.sqrt(E))
-    return bf + acc + 4.0 * U32 * D64
+    return rep + acc + 4.0 * U32 * D64
 
 
 def fp32_rel_tol() -> float:

@@ -210,6 +210,43 @@ def _round_bf16(x32):
     return r.astype(np.uint32).view(np.float32)
 
 
+def test_split_bf16_bound_covers_simulated_fp32_gram():
+    # x = hi + lo with hi = bf16(x), lo = bf16(x - hi); the Gram form
+    # simulated in FP32 (sequential sums) with the dot product
+    # hi.hi' + hi.lo' + lo.hi' and norms of hi + lo; every pair that would
+    # not be recomputed stays inside the split bound, which is far tighter
+    # than the BF16 one
+    X, pairs = synth.gaussian_with_near_duplicates(600, 64, seed=34)
+    hi = _round_bf16(X)
+    r = (X - hi).astype(np.float32)
+    lo = _round_bf16(r)
+    # x - hi is exact in FP32 and hi + lo is exactly representable
+    assert np.array_equal(r.astype(np.float64), X.astype(np.float64) - hi.astype(np.float64))
+    xt = (hi + lo).astype(np.float32)
+    assert np.array_equal(xt.astype(np.float64), hi.astype(np.float64) + lo.astype(np.float64))
+    n = np.zeros(600, dtype=np.float32)
+    for k in range(64):
+        n = n + xt[:, k] * xt[:, k]
+    dot = np.zeros((600, 600), dtype=np.float32)
+    for k in range(64):
+        dot = dot + np.outer(hi[:, k], hi[:, k]).astype(np.float32)
+        dot = dot + np.outer(hi[:, k], lo[:, k]).astype(np.float32)
+        dot = dot + np.outer(lo[:, k], hi[:, k]).astype(np.float32)
+    G = (n[:, None] + n[None, :]) - np.float32(2.0) * dot
+    Dg = np.sqrt(np.maximum(G, 0)).astype(np.float64)
+    D = squareform(pdist(X.astype(np.float64)))
+    norms = np.linalg.norm(X.astype(np.float64), axis=1)
+    bound = edm.gram_bound(norms[:, None], norms[None, :], D, 64, split=True)
+    recompute = G <= 0.25 * (n[:, None] + n[None, :])
+    assert np.all((np.abs(Dg - D) <= bound) | recompute)
+    assert np.all(recompute[pairs[:, 0], pairs[:, 1]])
+    # the bound is tight enough to mean something: about 1e-4 of the
+    # distance, and more than 50 times below the BF16 bound
+    bf16 = edm.gram_bound(norms[:, None], norms[None, :], D, 64)
+    assert np.median(bound[~recompute] / D[~recompute]) < 1e-4
+    assert np.all(bound[~recompute] * 50 < bf16[~recompute])
+
+
 def test_bf16_rounding_helper():
     vals = np.array([1.0, 1.00390625, 1.005859375, -3.0, 0.0], dtype=np.float32)
     # 1 + 2^-8 is the midpoint between 1 and 1 + 2^-7: ties to even -> 1
