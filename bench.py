@@ -184,23 +184,71 @@ def row_strict(torch, tdmap, synth):
     return out
 
 
+def row_paper_grid(torch, tdmap, synth):
+    """The paper's measurement grid: N = 1024 .. 30720 in steps of 1024, every
+    strategy with 16 x 16 blocks, the dummy kernel and the EDM with d = 1 and
+    d = 4 (full N x N output), reported as I = t_BB / t_strategy; plus I as a
+    function of d = 1..4 at N = 30720.  Not part of the default run (about a
+    minute)."""
+    strats = ("ltm", "bb", "utm", "rb", "rec")
+    Nmax = 30720
+    buf = torch.empty(Nmax * Nmax, dtype=torch.float32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pts = {d: torch.from_numpy(synth.uniform_points(Nmax, d, seed=synth.workload_seed(2) + d)).cuda()
+           for d in (1, 2, 3, 4)}
+
+    def edm_us(s, N, d):
+        X = pts[d][:N]
+        D = buf[: N * N].view(N, N)
+        return _med_ms(lambda: tdmap.edm(X, layout="full", strategy=s, rho=16, out=D), 5, 1) * 1e3
+
+    grid = {"N": [], "dummy_I": {s: [] for s in strats}, "edm_d1_I": {s: [] for s in strats},
+            "edm_d4_I": {s: [] for s in strats}, "edm_d1_bb_us": [], "dummy_bb_us": []}
+    for N in range(1024, Nmax + 1, 1024):
+        grid["N"].append(N)
+        t = {s: _med_ms(lambda s=s: tdmap.dummy(s, N, 16, sink=sink), 5, 1) * 1e3 for s in strats}
+        e1 = {s: edm_us(s, N, 1) for s in strats}
+        e4 = {s: edm_us(s, N, 4) for s in strats}
+        for s in strats:
+            grid["dummy_I"][s].append(round(t["bb"] / t[s], 4))
+            grid["edm_d1_I"][s].append(round(e1["bb"] / e1[s], 4))
+            grid["edm_d4_I"][s].append(round(e4["bb"] / e4[s], 4))
+        grid["dummy_bb_us"].append(round(t["bb"], 2))
+        grid["edm_d1_bb_us"].append(round(e1["bb"], 2))
+        log(f"grid N={N}: dummy I(ltm) {grid['dummy_I']['ltm'][-1]}, "
+            f"edm d=1 I(ltm) {grid['edm_d1_I']['ltm'][-1]}")
+    by_d = {}
+    for d in (1, 2, 3, 4):
+        e = {s: edm_us(s, Nmax, d) for s in strats}
+        by_d[f"d{d}"] = {s: round(e["bb"] / e[s], 4) for s in strats}
+    grid["I_by_d_N30720"] = by_d
+    mean = lambda v: round(sum(v) / len(v), 4)
+    grid["mean_I"] = {k: {s: mean(grid[k][s]) for s in strats}
+                      for k in ("dummy_I", "edm_d1_I", "edm_d4_I")}
+    del buf
+    return grid
+
+
 def row_gram(torch, tdmap, synth):
-    """100000 points, d = 64, BF16 Gram form on MFMA, packed output."""
+    """100000 points, d = 64, BF16 Gram form on MFMA, packed output; beside
+    it the split form (hi + lo, three MFMA products)."""
     N, d = 100000, 64
     X, _ = synth.gaussian_with_near_duplicates(N, d, seed=synth.workload_seed(3))
     Xd = torch.from_numpy(X).cuda()
     D = torch.empty(N * (N + 1) // 2, dtype=torch.float32, device="cuda")
-    ws = torch.empty(tdmap.tdmap_workspace_size(tdmap.OP_EDM, N, d, 0, 0, tdmap.BF16_GRAM),
+    ws = torch.empty(tdmap.tdmap_workspace_size(tdmap.OP_EDM, N, d, 0, 0, tdmap.BF16X3_GRAM),
                      dtype=torch.uint8, device="cuda")
-    fn = lambda: tdmap.edm(Xd, layout="packed", rho=0, precision="bf16_gram", out=D,
-                           workspace=ws)
-    t = _med_ms(fn, 10)
     pairs = N * (N + 1) // 2
-    flops = 2.0 * d * pairs
+    res = {"N": N, "d": d, "pairs": pairs}
+    for prec, key in (("bf16_gram", ""), ("bf16x3_gram", "split_")):
+        fn = lambda: tdmap.edm(Xd, layout="packed", rho=0, precision=prec, out=D, workspace=ws)
+        t = _med_ms(fn, 10)
+        flops = (2.0 if not key else 6.0) * d * pairs
+        res.update({key + "us": t * 1e3, key + "pairs_per_s": pairs / (t * 1e-3),
+                    key + "hbm_frac": 4 * pairs / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    key + "mfma_frac_bf16": flops / (t * 1e-3) / 2.5e15})
     del D
-    return {"N": N, "d": d, "pairs": pairs, "us": t * 1e3, "pairs_per_s": pairs / (t * 1e-3),
-            "hbm_frac": 4 * pairs / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "mfma_frac_bf16": flops / (t * 1e-3) / 2.5e15}
+    return res
 
 
 def row_batched(torch, tdmap, synth):
@@ -302,6 +350,7 @@ def main():
         from paper_1308_1419_amd import synth, tdmap
         fn = {"edm_n1024_d3_full": row_small, "stress_n20000_d3": row_stress,
               "mapcost_n30000": row_mapcost, "strict_n30000_d3": row_strict,
+              "paper_grid_rho16": row_paper_grid,
               "gram_n100000_d64_packed": row_gram,
               "batched_s4096_n64_4096_d3": row_batched}[args.row]
         print(json.dumps({args.row: fn(torch, tdmap, synth)}), flush=True)

@@ -69,8 +69,12 @@ typedef enum { TDMAP_FULL = 0, TDMAP_PACKED = 1, TDMAP_PACKED_STRICT = 2 } tdmap
 
 typedef enum {
     TDMAP_FP32 = 0,      /* difference form sqrt(sum_k (x_ik - x_jk)^2) in FP32 */
-    TDMAP_BF16_GRAM = 1  /* ||x||^2 + ||y||^2 - 2 x.y with BF16 MFMA, FP32 accumulate,
+    TDMAP_BF16_GRAM = 1, /* ||x||^2 + ||y||^2 - 2 x.y with BF16 MFMA, FP32 accumulate,
                             FP32 difference-form recompute of near-zero distances */
+    TDMAP_BF16X3_GRAM = 2 /* the same Gram form with x = hi + lo, hi = bf16(x),
+                             lo = bf16(x - hi) and x.y taken as hi.hi' + hi.lo' + lo.hi'
+                             (three MFMA products): representation error 2^-16 |x|
+                             instead of 2^-8 |x| */
 } tdmap_precision;
 
 typedef enum { TDMAP_OP_EDM = 0, TDMAP_OP_BACKWARD = 1, TDMAP_OP_BATCHED = 2 } tdmap_op;
@@ -117,8 +121,15 @@ int tdmap_map_blocks_nodiag(uint64_t lambda0, uint64_t count, uint32_t *ij, void
  *              64, 128, 256 : (LTM, BB) rho x rho cell tiles per 256-thread
  *                          work-group, four consecutive cells per thread;
  *              0         : (LTM, BB) tile chosen by the autotuner.
- *   precision TDMAP_FP32 for every strategy; TDMAP_BF16_GRAM only with
- *            TDMAP_LTM, TDMAP_PACKED and rho = 0 or 128.
+ *   precision TDMAP_FP32 for every strategy; TDMAP_BF16_GRAM and
+ *            TDMAP_BF16X3_GRAM only with TDMAP_LTM, TDMAP_PACKED and rho = 0
+ *            or 128.  Their error per pair that is not recomputed is at most
+ *            r (|x_i| + |x_j|) + E / (D - r (|x_i| + |x_j|)) + 4 u32 D with
+ *            r = 2^-8 (BF16) or 2^-16 (BF16X3), u32 = 2^-24 and E the FP32
+ *            accumulation bound 2 (m d + 4) u32 (|x_i|^2 + |x_j|^2)(1 + 2^-8)^2
+ *            (m = 1 or 3; BF16X3 adds 2^-15 (1 + 2^-8)^2 |x_i| |x_j| for the
+ *            dropped lo.lo'); pairs with G <= (n_i + n_j)/4 are recomputed in
+ *            FP32 difference form and meet the FP32 rule below.
  *   layout   TDMAP_PACKED_STRICT only with TDMAP_FP32, LTM or BB and
  *            rho = 0, 1 (LTM), 64, 128 or 256.
  *   workspace device scratch of at least

@@ -243,8 +243,8 @@ size_t tdmap_workspace_size(int32_t op, int64_t N, int32_t d, int32_t num_sets, 
   if (N < 0 || d < 1) return 0;
   switch (op) {
     case TDMAP_OP_EDM:
-      if (flags != TDMAP_BF16_GRAM) return 0;
-      return tdmap::gram_workspace_bytes(N, d);
+      if (flags != TDMAP_BF16_GRAM && flags != TDMAP_BF16X3_GRAM) return 0;
+      return tdmap::gram_workspace_bytes(N, d, flags == TDMAP_BF16X3_GRAM);
     case TDMAP_OP_BACKWARD:
       if (!flags || d > 4) return 0;
       if (rho == 0)
@@ -267,17 +267,20 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int64
   int st = validate_edm_common(X, N, d, ldx, D, ldd, layout);
   if (st != TDMAP_OK) return st;
   if (strategy < TDMAP_LTM || strategy > TDMAP_REC) return TDMAP_ERR_INVALID;
-  if (precision != TDMAP_FP32 && precision != TDMAP_BF16_GRAM) return TDMAP_ERR_INVALID;
+  if (precision != TDMAP_FP32 && precision != TDMAP_BF16_GRAM && precision != TDMAP_BF16X3_GRAM)
+    return TDMAP_ERR_INVALID;
   if (!(rho == 0 || rho == 1 || is_cell_rho(rho) || rho == 64 || rho == 128 || rho == 256))
     return TDMAP_ERR_INVALID;
-  if (precision == TDMAP_BF16_GRAM) {
+  if (precision != TDMAP_FP32) {
+    const bool split = precision == TDMAP_BF16X3_GRAM;
     if (strategy != TDMAP_LTM || layout != TDMAP_PACKED || (rho != 0 && rho != 128))
       return TDMAP_ERR_UNSUPPORTED;
     if (N == 0) return TDMAP_OK;
     if (tri(ceil_div((uint64_t)N, 128)) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
-    if (workspace == nullptr || ws_bytes < tdmap::gram_workspace_bytes(N, d))
+    if (workspace == nullptr || ws_bytes < tdmap::gram_workspace_bytes(N, d, split))
       return TDMAP_ERR_WORKSPACE;
-    TD_HIP(tdmap::launch_gram(X, N, d, ldx, D, workspace, (hipStream_t)stream), "tdmap_edm");
+    TD_HIP(tdmap::launch_gram(X, N, d, ldx, D, workspace, split, (hipStream_t)stream),
+           "tdmap_edm");
     return TDMAP_OK;
   }
   const bool tiled = !is_cell_rho(rho);

@@ -13,6 +13,12 @@
 // the pair is close relative to its norms, where the Gram form cancels),
 // recomputes the distance exactly in FP32 difference form from the FP32
 // points; otherwise it stores sqrt(G).
+//
+// Split mode (precision BF16X3): each point is held as x = hi + lo with
+// hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in FP32, and hi + lo
+// is exact in FP32), the norms are those of hi + lo, and the dot product is
+// hi.hi' + hi.lo' + lo.hi', three MFMA products into the same FP32
+// accumulator; only lo.lo' (below 2^-16 of |x||y|) is dropped.
 #include "device.h"
 #include "kernels.h"
 
@@ -33,9 +39,11 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// One thread per padded point: BF16 copy (zero padded) and its squared norm.
+// One thread per padded point: BF16 copy (zero padded) and the squared norm
+// of the represented point; with Xlo != nullptr also the low parts.
 __global__ __launch_bounds__(256) void gram_prologue_kernel(const float *__restrict__ X, int64_t N, int d,
                                                             int64_t ldx, uint16_t *__restrict__ Xb,
+                                                            uint16_t *__restrict__ Xlo,
                                                             float *__restrict__ nrm, int64_t Npad,
                                                             int KP) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -45,7 +53,12 @@ __global__ __launch_bounds__(256) void gram_prologue_kernel(const float *__restr
     const float v = (p < N && k < d) ? X[p * ldx + k] : 0.0f;
     const uint16_t b = bf16_rne(v);
     Xb[p * KP + k] = b;
-    const float r = bf16_to_f32(b);
+    float r = bf16_to_f32(b);
+    if (Xlo != nullptr) {
+      const uint16_t c = bf16_rne(v - r);
+      Xlo[p * KP + k] = c;
+      r += bf16_to_f32(c);
+    }
     s = __builtin_fmaf(r, r, s);
   }
   nrm[p] = s;
@@ -101,7 +114,9 @@ __device__ __forceinline__ int row_shift(int rr) {
   return ((m * (m + 1)) >> 1) & 3;
 }
 
-__global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t lam0, uint32_t nblk) {
+template <bool SPLIT>
+__global__ __launch_bounds__(256, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs a, uint32_t lam0,
+                                                                      uint32_t nblk) {
   // Work-groups are dispatched round-robin over the eight XCDs (block b on
   // XCD b mod 8).  Each XCD is given one contiguous range of lambda, so the
   // tiles an XCD runs back to back share their row block and sweep the
@@ -140,12 +155,22 @@ __global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t 
   // lane l supplies row (l % 32) of a 32-row block and the 8 features
   // [8 (l / 32), 8 (l / 32) + 8) of each 16-feature step; B uses the same
   // assignment for its points, so the product is x_i . x_j.
+  const uint16_t *__restrict__ Xl = a.Xlo;
   for (int k = 0; k < KP; k += 16) {
-    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Xb + (rw + lr) * KP + k + lk);
+    const int64_t ao = (rw + lr) * KP + k + lk;
+    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Xb + ao);
+    bf16x8 al;
+    if constexpr (SPLIT) al = *reinterpret_cast<const bf16x8 *>(Xl + ao);
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) {
       if (bj < nbj) {
-        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Xb + (col0 + bj * 32 + lr) * KP + k + lk);
+        const int64_t bo = (col0 + bj * 32 + lr) * KP + k + lk;
+        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Xb + bo);
+        if constexpr (SPLIT) {
+          const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(Xl + bo);
+          acc[bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bv, acc[bj], 0, 0, 0);
+          acc[bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bl, acc[bj], 0, 0, 0);
+        }
         acc[bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[bj], 0, 0, 0);
       }
     }
@@ -238,31 +263,38 @@ __global__ __launch_bounds__(256, 4) void gram_tile_kernel(GramArgs a, uint32_t 
   }
 }
 
-size_t gram_workspace_bytes(int64_t N, int d) {
+size_t gram_workspace_bytes(int64_t N, int d, bool split) {
   const int64_t Npad = (N + kGramTile - 1) / kGramTile * kGramTile;
   const int64_t KP = (d + 15) / 16 * 16;
-  return (size_t)Npad * (size_t)KP * 2 + (size_t)Npad * 4;
+  return (size_t)Npad * (size_t)KP * 2 * (split ? 2 : 1) + (size_t)Npad * 4;
 }
 
-hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws,
+hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws, bool split,
                        hipStream_t stream) {
   if (N == 0) return hipSuccess;
   const int64_t Npad = (N + kGramTile - 1) / kGramTile * kGramTile;
   const int KP = (d + 15) / 16 * 16;
+  // workspace: hi parts, [lo parts,] norms
   uint16_t *Xb = reinterpret_cast<uint16_t *>(ws);
-  float *nrm = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + (size_t)Npad * KP * 2);
+  uint16_t *Xlo = split ? Xb + (size_t)Npad * KP : nullptr;
+  float *nrm = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) +
+                                         (size_t)Npad * KP * 2 * (split ? 2 : 1));
   hipLaunchKernelGGL(gram_prologue_kernel, dim3((uint32_t)((Npad + 255) / 256)), dim3(256), 0, stream,
-                     X, N, d, ldx, Xb, nrm, Npad, KP);
+                     X, N, d, ldx, Xb, Xlo, nrm, Npad, KP);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  GramArgs a{X, N, d, ldx, Xb, nrm, KP, D};
+  GramArgs a{X, N, d, ldx, Xb, Xlo, nrm, KP, D};
   const uint64_t nb = (uint64_t)(Npad / kGramTile);
   const uint64_t T = nb * (nb + 1) / 2;
   const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
   for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
     const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
-    hipLaunchKernelGGL(gram_tile_kernel, dim3((uint32_t)c), dim3(256), 0, stream, a, (uint32_t)l0,
-                       (uint32_t)c);
+    if (split)
+      hipLaunchKernelGGL(gram_tile_kernel<true>, dim3((uint32_t)c), dim3(256), 0, stream, a,
+                         (uint32_t)l0, (uint32_t)c);
+    else
+      hipLaunchKernelGGL(gram_tile_kernel<false>, dim3((uint32_t)c), dim3(256), 0, stream, a,
+                         (uint32_t)l0, (uint32_t)c);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;

@@ -80,14 +80,16 @@ struct GramArgs {
   int d;
   int64_t ldx;
   const uint16_t *Xb;  // BF16 points, padded: ceil(N/128)*128 rows of KP features
-  const float *nrm;    // squared norms of the BF16 points
+  const uint16_t *Xlo; // split mode: BF16 low parts x - hi, same layout; else nullptr
+  const float *nrm;    // squared norms of the represented points
   int KP;              // features padded to a multiple of 16
   float *D;            // packed output
 };
 
-// BF16 Gram-form EDM (packed), workspace of gram_workspace_bytes(N, d).
-size_t gram_workspace_bytes(int64_t N, int d);
-hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws,
+// BF16 Gram-form EDM (packed), workspace of gram_workspace_bytes(N, d,
+// split); split = the hi + lo representation with three products.
+size_t gram_workspace_bytes(int64_t N, int d, bool split);
+hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws, bool split,
                        hipStream_t stream);
 
 // Packed layout written as a linear sweep (g at one-cell granularity).

@@ -25,12 +25,12 @@ LIB_PATH = os.path.join(_HERE, "libtdmap.so")
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = range(5)
 LTM, BB, UTM, RB, REC = range(5)
 FULL, PACKED, PACKED_STRICT = 0, 1, 2
-FP32, BF16_GRAM = 0, 1
+FP32, BF16_GRAM, BF16X3_GRAM = 0, 1, 2
 OP_EDM, OP_BACKWARD, OP_BATCHED = 0, 1, 2
 
 STRATEGIES = {"ltm": LTM, "bb": BB, "utm": UTM, "rb": RB, "rec": REC}
 LAYOUTS = {"full": FULL, "packed": PACKED, "strict": PACKED_STRICT}
-PRECISIONS = {"fp32": FP32, "bf16_gram": BF16_GRAM}
+PRECISIONS = {"fp32": FP32, "bf16_gram": BF16_GRAM, "bf16x3_gram": BF16X3_GRAM}
 
 
 class TdmapError(RuntimeError):

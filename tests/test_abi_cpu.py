@@ -98,6 +98,26 @@ def test_validation_rejects_before_launch(lib):
     assert L.tdmap_count_waste(0, 100, 16, None, None) == tdmap.ERR_INVALID
 
 
+def test_gram_workspace_sizes(lib):
+    # BF16 copy (padded to 128 points x a multiple of 16 features) and the
+    # norms; the split form holds a second BF16 array for the low parts
+    N, d = 1000, 50
+    Npad, KP = 1024, 64
+    assert tdmap.tdmap_workspace_size(tdmap.OP_EDM, N, d, 0, 0, tdmap.BF16_GRAM) == \
+        Npad * KP * 2 + Npad * 4
+    assert tdmap.tdmap_workspace_size(tdmap.OP_EDM, N, d, 0, 0, tdmap.BF16X3_GRAM) == \
+        2 * Npad * KP * 2 + Npad * 4
+    L = tdmap._load()
+    # the split form is validated like the BF16 form: packed LTM only, and a
+    # workspace of the size above
+    assert L.tdmap_edm(8, N, d, d, 16, N, tdmap.FULL, 0, 0, tdmap.BF16X3_GRAM, 8, 1 << 30,
+                       None) == tdmap.ERR_UNSUPPORTED
+    assert L.tdmap_edm(8, N, d, d, 16, 0, tdmap.PACKED, 0, 0, tdmap.BF16X3_GRAM, 8,
+                       Npad * KP * 2 + Npad * 4, None) == tdmap.ERR_WORKSPACE
+    assert L.tdmap_edm(8, N, d, d, 16, 0, tdmap.PACKED, 0, 0, 3, 8, 1 << 30, None) \
+        == tdmap.ERR_INVALID
+
+
 def test_fp32_needs_no_workspace(lib):
     for rho in (0, 8, 16, 32, 64, 128, 256):
         assert tdmap.tdmap_workspace_size(tdmap.OP_EDM, 30000, 3, 0, rho, tdmap.FP32) == 0
