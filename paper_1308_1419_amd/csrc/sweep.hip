@@ -68,6 +68,17 @@ __device__ __forceinline__ void load_pt(const float *__restrict__ X, int64_t ldx
   for (int k = 0; k < D; ++k) v[k] = X[p * ldx + k];
 }
 
+// Column point c of a uniform base, addressed by a 32-bit byte offset
+// (c * row_bytes < 2^32 is checked by the caller): the load then takes a
+// scalar base and one vector offset, with no 64-bit index arithmetic.
+template <int D>
+__device__ __forceinline__ void load_pt32(const float *__restrict__ X, uint32_t row_bytes,
+                                          uint32_t c, float (&v)[D]) {
+  const float *p = reinterpret_cast<const float *>(reinterpret_cast<const char *>(X) + c * row_bytes);
+#pragma unroll
+  for (int k = 0; k < D; ++k) v[k] = p[k];
+}
+
 // One wave writes SW_G consecutive 1 KB pieces (SW_G float4 stores per
 // lane, each covering 256 consecutive positions).  When the wave's first
 // cell lies in a row of at least SW_G * 256 cells, its positions cover at
@@ -79,7 +90,9 @@ constexpr int SW_G = 4;
 constexpr int SW_WAVE = 256 * SW_G;       // positions per wave
 constexpr int SW_BLOCK = 4 * SW_WAVE;     // positions per work-group
 
-template <int D, bool STRICT>
+// OFF32: contiguous points (ldx == D) and N * D * 4 < 2^32, so a column
+// offset is a 32-bit multiple of the constant D * 4.
+template <int D, bool STRICT, bool OFF32>
 __global__ __launch_bounds__(256) void edm_sweep_kernel(const float *__restrict__ X, int64_t N,
                                                         int64_t ldx, float *__restrict__ out,
                                                         uint64_t total, uint64_t e_base) {
@@ -106,9 +119,16 @@ __global__ __launch_bounds__(256) void edm_sweep_kernel(const float *__restrict_
     for (int g = 0; g < SW_G; ++g)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const uint64_t j = jw + 256 * g + 4 * l + q;
-        lo[g][q] = j < len_w;
-        load_pt<D>(X, ldx, lo[g][q] ? j : j - len_w, xj[g][q]);
+        if constexpr (OFF32) {
+          // every column is below N < 2^31
+          const uint32_t j = (uint32_t)jw + 256 * g + 4 * l + q;
+          lo[g][q] = j < (uint32_t)len_w;
+          load_pt32<D>(X, D * 4u, lo[g][q] ? j : j - (uint32_t)len_w, xj[g][q]);
+        } else {
+          const uint64_t j = jw + 256 * g + 4 * l + q;
+          lo[g][q] = j < len_w;
+          load_pt<D>(X, ldx, lo[g][q] ? j : j - len_w, xj[g][q]);
+        }
       }
 #pragma unroll
     for (int g = 0; g < SW_G; ++g) {
@@ -215,9 +235,11 @@ __global__ __launch_bounds__(256) void edm_batched_sweep_kernel(
       for (int g = 0; g < SW_G; ++g)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const uint64_t j = jw + 256 * g + 4 * l + q;
-          lo[g][q] = j <= iw;
-          load_pt<D>(Xs, D, lo[g][q] ? j : j - iw - 1, xj[g][q]);
+          // columns are below the set's size n, and n * D * 4 < 2^32: a set
+          // that large would need n(n+1)/2 > 2^53 output cells
+          const uint32_t j = (uint32_t)jw + 256 * g + 4 * l + q;
+          lo[g][q] = j <= (uint32_t)iw;
+          load_pt32<D>(Xs, D * 4u, lo[g][q] ? j : j - (uint32_t)iw - 1, xj[g][q]);
         }
 #pragma unroll
       for (int g = 0; g < SW_G; ++g) {
@@ -278,19 +300,28 @@ __global__ __launch_bounds__(256) void edm_batched_sweep_kernel(
   }
 }
 
-template <int D, bool STRICT>
+template <int D, bool STRICT, bool OFF32>
 static hipError_t launch_sweep_t(const EdmArgs &a) {
   const uint64_t total = STRICT ? (uint64_t)a.N * (uint64_t)(a.N - 1) / 2
                                 : (uint64_t)a.N * (uint64_t)(a.N + 1) / 2;
   const uint64_t per_launch = (uint64_t)SW_BLOCK * (((uint64_t)1 << 31) / 256);
   for (uint64_t b = 0; b < total; b += per_launch) {
     const uint64_t c = total - b < per_launch ? total - b : per_launch;
-    hipLaunchKernelGGL((edm_sweep_kernel<D, STRICT>), dim3((uint32_t)((c + SW_BLOCK - 1) / SW_BLOCK)),
+    hipLaunchKernelGGL((edm_sweep_kernel<D, STRICT, OFF32>), dim3((uint32_t)((c + SW_BLOCK - 1) / SW_BLOCK)),
                        dim3(256), 0, a.stream, a.X, a.N, a.ldx, a.D, b + c, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+template <int D>
+static hipError_t launch_sweep_d(const EdmArgs &a) {
+  const bool strict = a.layout == kLayoutStrict;
+  const bool off32 = a.ldx == D && (uint64_t)a.N * D * 4u < ((uint64_t)1 << 32);
+  if (strict)
+    return off32 ? launch_sweep_t<D, true, true>(a) : launch_sweep_t<D, true, false>(a);
+  return off32 ? launch_sweep_t<D, false, true>(a) : launch_sweep_t<D, false, false>(a);
 }
 
 bool sweep_supported(const EdmArgs &a) {
@@ -300,12 +331,11 @@ bool sweep_supported(const EdmArgs &a) {
 
 hipError_t launch_sweep(const EdmArgs &a) {
   if (a.N == 0) return hipSuccess;
-  const bool strict = a.layout == kLayoutStrict;
   switch (a.d) {
-    case 1: return strict ? launch_sweep_t<1, true>(a) : launch_sweep_t<1, false>(a);
-    case 2: return strict ? launch_sweep_t<2, true>(a) : launch_sweep_t<2, false>(a);
-    case 3: return strict ? launch_sweep_t<3, true>(a) : launch_sweep_t<3, false>(a);
-    case 4: return strict ? launch_sweep_t<4, true>(a) : launch_sweep_t<4, false>(a);
+    case 1: return launch_sweep_d<1>(a);
+    case 2: return launch_sweep_d<2>(a);
+    case 3: return launch_sweep_d<3>(a);
+    case 4: return launch_sweep_d<4>(a);
     default: return hipErrorInvalidValue;
   }
 }
