@@ -125,7 +125,9 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
   const uint32_t b = blockIdx.x, xcd = b & 7, per = nblk >> 3, extra = nblk & 7;
   uint32_t I, J;
   g_lambda(lam0 + xcd * per + (xcd < extra ? xcd : extra) + (b >> 3), I, J);
-  const int w = threadIdx.x >> 6;
+  I = __builtin_amdgcn_readfirstlane(I);  // uniform: keep the tile origin scalar
+  J = __builtin_amdgcn_readfirstlane(J);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l = threadIdx.x & 63;
   const int lr = l & 31;
   const int lk = (l >> 5) * 8;
@@ -220,31 +222,43 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
     }
     // the wave reads back its own LDS writes: no barrier needed
     if (full_rows) {
+      // Row rw + m (m < 32) starts at T(rw) + col0 + m rw + m(m+1)/2: a
+      // uniform base and a 32-bit offset (m rw < 32 N < 2^30 under the
+      // 32-bit tile index), with the row's shift row_shift(m) (rw is a
+      // multiple of 32, so T(rw) and m rw add nothing mod 4).
+      float *__restrict__ outw = out + tri64((uint64_t)rw) + (uint64_t)col0;
+      const uint32_t rw32 = (uint32_t)rw;
+      auto row_off = [&](uint32_t m) { return m * rw32 + ((m * (m + 1)) >> 1); };
+      // cell offset -> address as a 32-bit byte offset from the uniform base
+      auto at = [&](uint32_t e) {
+        return reinterpret_cast<float *>(reinterpret_cast<char *>(outw) + e * 4u);
+      };
       // whole aligned chunks, two rows per instruction
 #pragma unroll 2
       for (int p = 0; p < kGramRows / 2; ++p) {
         const int r = 2 * p + (l >> 5);
-        const uint64_t first = tri64((uint64_t)(rw + 16 * vh + r)) + (uint64_t)col0;
-        const int sh = (int)(first & 3);
+        const uint32_t m = 16 * vh + r;
+        const int sh = row_shift(r);
         if (h > 0 || sh == 0) {
           const f4 v4 = *reinterpret_cast<const f4 *>(&st[r][4 * h]);
-          __builtin_nontemporal_store(v4, reinterpret_cast<f4 *>(out + first - sh + 4 * h));
+          __builtin_nontemporal_store(v4, reinterpret_cast<f4 *>(at(row_off(m) - sh + 4 * h)));
         }
       }
       // the partial chunks at both ends of every row: the 4 - sh head cells
       // (columns 0 .. 3 - sh) and the sh tail cells (columns 128 - sh .. 127),
       // one row per lane, four instructions for all 16 rows
       if (l < kGramRows) {
-        const uint64_t first = tri64((uint64_t)(rw + 16 * vh + l)) + (uint64_t)col0;
-        const int sh = (int)(first & 3);
+        const uint32_t m = 16 * vh + l;
+        const int sh = row_shift(l);
         if (sh != 0) {
+          const uint32_t o0 = row_off(m);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int c = q < 4 - sh ? q : kGramTile - 4 + q;
             // plain (cached) store: the neighbouring tile writes the rest
             // of this 16-byte chunk, and the two halves then meet in L2
             // instead of reaching HBM as two partial line writes
-            out[first + c] = st[l][c + sh];
+            *at(o0 + c) = st[l][c + sh];
           }
         }
       }
