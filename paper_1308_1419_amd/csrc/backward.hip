@@ -137,7 +137,7 @@ template <int TS, int D, int LAYOUT, bool DET>
 __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
   constexpr int H = TS / 2;
   constexpr int Q = H / 16;      // columns per lane
-  const uint32_t lam = lam0 + blockIdx.x;
+  const uint32_t lam = lam0 + xcd_contiguous(blockIdx.x, gridDim.x);
   uint32_t I, J;
   g_lambda(lam, I, J);
   const int t = threadIdx.x;
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
 template <int D, int LAYOUT, bool DET>
 __global__ __launch_bounds__(256) void edm_bwd_tile256(BwdArgs a, uint32_t lam0) {
   constexpr int TS = 256;
-  const uint32_t lam = lam0 + blockIdx.x;
+  const uint32_t lam = lam0 + xcd_contiguous(blockIdx.x, gridDim.x);
   uint32_t I, J;
   g_lambda(lam, I, J);
   const int t = threadIdx.x;

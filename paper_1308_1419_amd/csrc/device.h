@@ -64,6 +64,17 @@ __device__ __forceinline__ void g_nodiag(uint32_t lam, uint32_t &i, uint32_t &j)
   j = (uint32_t)(lam - t);
 }
 
+// Work-group b of a 1D launch of nblk work-groups runs on XCD b mod 8 (the
+// dispatcher deals work-groups to the eight XCDs in turn).  This returns a
+// block index under which every XCD owns one contiguous range: tiles that
+// are neighbours in lambda (the same tile row, adjacent columns) then run on
+// the same XCD at about the same time, so the cache lines their row segments
+// share meet in that XCD's L2 instead of travelling to HBM twice.
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t nblk) {
+  const uint32_t xcd = b & 7, per = nblk >> 3, extra = nblk & 7;
+  return xcd * per + (xcd < extra ? xcd : extra) + (b >> 3);
+}
+
 // The paper's three ways of taking the row of g(lambda) (Sec. III-A), kept
 // for the mapping-cost measurements; only variant 0 is exact everywhere.
 //   0: the fix-up map above (rsq guess + integer correction);

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void edm_tile_kernel(EdmArgs a, uint32_t lam0)
     I = blockIdx.y;
     if (J > I) return;
   } else {
-    g_lambda(lam0 + blockIdx.x, I, J);
+    g_lambda(lam0 + xcd_contiguous(blockIdx.x, gridDim.x), I, J);
   }
   constexpr int V = VEC ? 4 : 1;    // cells per lane per row
   constexpr int LPR = TS / V;       // lanes per tile row
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void edm_tile256_kernel(const float *__restric
     I = blockIdx.y;
     if (J > I) return;
   } else {
-    g_lambda(lam0 + blockIdx.x, I, J);
+    g_lambda(lam0 + xcd_contiguous(blockIdx.x, gridDim.x), I, J);
   }
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lc = (threadIdx.x & 63) * 4;
