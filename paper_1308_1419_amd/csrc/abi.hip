@@ -61,9 +61,12 @@ void tuned_store(const TuneKey &k, int v) {
   g_tuned[k] = v;
 }
 
-// Runs launch(c) for every candidate c: one warm-up and `reps` timed runs,
-// median of the per-run times.  Returns the fastest candidate (0 on error,
-// with *status set).
+// Runs launch(c) for every candidate c: one warm-up each, then `reps`
+// rounds in which every candidate is timed once, median of its times.  The
+// rounds interleave the candidates because the device's speed drifts over a
+// burst of back-to-back launches (clocks settle), which would otherwise
+// favour whichever candidate is timed first.  Returns the fastest candidate
+// (0 on error, with *status set).
 template <class F>
 int autotune(const std::vector<int> &cands, hipStream_t s, F launch, int *status) {
   hipEvent_t ev[2];
@@ -73,19 +76,16 @@ int autotune(const std::vector<int> &cands, hipStream_t s, F launch, int *status
     g_last_error = "autotune: hipEventCreate failed";
     return 0;
   }
-  int best = 0;
-  float best_ms = 0.0f;
-  const int reps = 3;
-  for (int c : cands) {
-    hipError_t e = launch(c);
-    if (e != hipSuccess) {
-      *status = hip_fail(e, "autotune launch");
-      break;
-    }
-    std::vector<float> ms;
-    for (int r = 0; r < reps && *status == TDMAP_OK; ++r) {
-      e = hipEventRecord(ev[0], s);
-      if (e == hipSuccess) e = launch(c);
+  const int reps = 5;
+  std::vector<std::vector<float>> ms(cands.size());
+  for (size_t k = 0; k < cands.size() && *status == TDMAP_OK; ++k) {
+    const hipError_t e = launch(cands[k]);
+    if (e != hipSuccess) *status = hip_fail(e, "autotune launch");
+  }
+  for (int r = 0; r < reps && *status == TDMAP_OK; ++r) {
+    for (size_t k = 0; k < cands.size(); ++k) {
+      hipError_t e = hipEventRecord(ev[0], s);
+      if (e == hipSuccess) e = launch(cands[k]);
       if (e == hipSuccess) e = hipEventRecord(ev[1], s);
       if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
       if (e != hipSuccess) {
@@ -94,14 +94,19 @@ int autotune(const std::vector<int> &cands, hipStream_t s, F launch, int *status
       }
       float t = 0.0f;
       (void)hipEventElapsedTime(&t, ev[0], ev[1]);
-      ms.push_back(t);
+      ms[k].push_back(t);
     }
-    if (*status != TDMAP_OK) break;
-    std::sort(ms.begin(), ms.end());
-    const float med = ms[ms.size() / 2];
-    if (best == 0 || med < best_ms) {
-      best = c;
-      best_ms = med;
+  }
+  int best = 0;
+  float best_ms = 0.0f;
+  if (*status == TDMAP_OK) {
+    for (size_t k = 0; k < cands.size(); ++k) {
+      std::sort(ms[k].begin(), ms[k].end());
+      const float med = ms[k][ms[k].size() / 2];
+      if (best == 0 || med < best_ms) {
+        best = cands[k];
+        best_ms = med;
+      }
     }
   }
   (void)hipEventDestroy(ev[0]);
