@@ -119,8 +119,16 @@ int tdmap_map_blocks_nodiag(uint64_t lambda0, uint64_t count, uint32_t *ij, void
  *              8, 16, 32 : rho x rho threads per block, one cell per thread,
  *                          as the paper launches every strategy;
  *              64, 128, 256 : (LTM, BB) rho x rho cell tiles per 256-thread
- *                          work-group, four consecutive cells per thread;
- *              0         : (LTM, BB) tile chosen by the autotuner.
+ *                          work-group (full layout: four consecutive cells
+ *                          per thread and row; packed layouts: one cell per
+ *                          thread and row, except rho = 256 with D 16-byte
+ *                          aligned); LTM tiles are taken by g(lambda) with
+ *                          every XCD owning one contiguous range of lambda;
+ *              0         : (LTM, BB) chosen by the autotuner among the
+ *                          tiles (and, for LTM with a packed layout and an
+ *                          aligned D, the sweep rho = 1), timed on the
+ *                          first call for a (layout, strategy, d, size)
+ *                          class.
  *   precision TDMAP_FP32 for every strategy; TDMAP_BF16_GRAM and
  *            TDMAP_BF16X3_GRAM only with TDMAP_LTM, TDMAP_PACKED and rho = 0
  *            or 128.  Their error per pair that is not recomputed is at most
