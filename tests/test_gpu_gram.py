@@ -55,7 +55,7 @@ def _check_rows(X, rows, got_rows, split=False):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("N", [1, 2, 127, 128, 129, 300, 1000])
+@pytest.mark.parametrize("N", [1, 2, 63, 64, 65, 127, 128, 129, 300, 1000])
 @pytest.mark.parametrize("d", [1, 3, 16, 64, 100])
 def test_gram_small(N, d, prec):
     _require_gpu()
@@ -115,7 +115,7 @@ def test_gram_workload_full_size(prec):
     torch.cuda.synchronize()
     rows = set(synth.sample_rows(N, 512, seed=11))
     rows.update(int(max(c, s)) for c, s in pairs[:200])
-    rows.update({127, 128, 99967, 99968})
+    rows.update({63, 64, 127, 128, 99967, 99968})
     rows = sorted(rows)
     got_rows = []
     for i in rows:
