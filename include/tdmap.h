@@ -214,6 +214,17 @@ size_t tdmap_workspace_size(int32_t op, int64_t N, int32_t d, int32_t num_sets,
                             int32_t rho, int32_t flags);
 
 /*
+ * Write-stream reference for the roofline: sets buf[0 .. n) to `value` with
+ * one 16-byte non-temporal store per thread, consecutive threads on
+ * consecutive chunks.  Not part of the paper's method; it measures the
+ * store rate the device reaches on a plain linear stream, against which the
+ * EDM's store rate is read.
+ *   buf  device, 16-byte aligned, n floats.
+ * Errors: INVALID for a NULL or misaligned buf with n > 0.
+ */
+int tdmap_stream_fill(float *buf, uint64_t n, float value, void *stream);
+
+/*
  * Launch statistics of a strategy, in closed form (host only): out[0] =
  * blocks launched, out[1] = fully idle blocks (blocks that write no cell),
  * out[2] = idle threads (threads that write no cell), for the one-cell-per-

@@ -405,6 +405,13 @@ int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets, const int
   return TDMAP_OK;
 }
 
+int tdmap_stream_fill(float *buf, uint64_t n, float value, void *stream) {
+  if (n == 0) return TDMAP_OK;
+  if (buf == nullptr || (reinterpret_cast<uintptr_t>(buf) & 15) != 0) return TDMAP_ERR_INVALID;
+  TD_HIP(tdmap::launch_stream_fill(buf, n, value, (hipStream_t)stream), "tdmap_stream_fill");
+  return TDMAP_OK;
+}
+
 int tdmap_waste_counts(int32_t strategy, int64_t N, int32_t rho, int64_t out[3]) {
   if (out == nullptr || N < 0 || rho < 1) return TDMAP_ERR_INVALID;
   return waste_closed_form(strategy, N, rho, out) ? TDMAP_OK : TDMAP_ERR_INVALID;

@@ -101,5 +101,7 @@ hipError_t launch_batched_sweep(const BatchArgs &a, int wgs_per_cu);
 // Fill n floats with a value (a kernel, not a memset, so it can sit in a
 // captured graph).
 hipError_t launch_fill(float *p, uint64_t n, float v, hipStream_t stream);
+// n floats = v with 16-byte non-temporal stores (p 16-byte aligned).
+hipError_t launch_stream_fill(float *p, uint64_t n, float v, hipStream_t stream);
 
 }  // namespace tdmap

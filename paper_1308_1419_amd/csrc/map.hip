@@ -79,6 +79,37 @@ hipError_t launch_map_blocks_variant(uint64_t lambda0, uint64_t count, int varia
   return hipSuccess;
 }
 
+// Write-stream reference: one thread per 16-byte chunk, non-temporal
+// stores, consecutive threads on consecutive chunks (the plainest store
+// stream a kernel can issue).  p is 16-byte aligned; the last n % 4 floats
+// are written by thread 0 of the last block.
+typedef float f4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void stream_fill_kernel(float *__restrict__ p, uint64_t chunks,
+                                                          uint64_t n, float v, uint64_t c0) {
+  const uint64_t c = c0 + (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c < chunks) {
+    const f4 x = {v, v, v, v};
+    __builtin_nontemporal_store(x, reinterpret_cast<f4 *>(p) + c);
+  }
+  if (c == chunks) {
+    for (uint64_t e = 4 * chunks; e < n; ++e) p[e] = v;
+  }
+}
+
+hipError_t launch_stream_fill(float *p, uint64_t n, float v, hipStream_t stream) {
+  const uint64_t chunks = n / 4;
+  // chunks + 1 threads (the extra one writes the tail), at most 2^31 per launch
+  const uint64_t per_launch = (uint64_t)1 << 31;
+  for (uint64_t c0 = 0; c0 <= chunks; c0 += per_launch) {
+    const uint64_t c = chunks + 1 - c0 < per_launch ? chunks + 1 - c0 : per_launch;
+    hipLaunchKernelGGL(stream_fill_kernel, dim3((uint32_t)((c + 255) / 256)), dim3(256), 0, stream,
+                       p, chunks, n, v, c0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_fill(float *p, uint64_t n, float v, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   uint64_t blocks = (n + 255) / 256;

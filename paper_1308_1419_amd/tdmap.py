@@ -60,6 +60,7 @@ def _load() -> ctypes.CDLL:
     sig = {
         "tdmap_map_blocks": ([u64, u64, vp, vp], ctypes.c_int),
         "tdmap_map_blocks_nodiag": ([u64, u64, vp, vp], ctypes.c_int),
+        "tdmap_stream_fill": ([vp, u64, ctypes.c_float, vp], ctypes.c_int),
         "tdmap_edm": ([vp, i64, i32, i64, vp, i64, i32, i32, i32, i32, vp, sz, vp],
                       ctypes.c_int),
         "tdmap_edm_backward": ([vp, i64, i32, i64, vp, i64, i32, vp, i32, i32, vp, sz, vp],
@@ -86,7 +87,7 @@ def _load() -> ctypes.CDLL:
 EXPORTED = (
     "tdmap_map_blocks", "tdmap_map_blocks_nodiag", "tdmap_edm", "tdmap_edm_backward", "tdmap_edm_batched",
     "tdmap_workspace_size", "tdmap_waste_counts", "tdmap_count_waste",
-    "tdmap_map_blocks_variant", "tdmap_dummy",
+    "tdmap_map_blocks_variant", "tdmap_dummy", "tdmap_stream_fill",
     "tdmap_tuned_rho", "tdmap_autotune_reset", "tdmap_status_string",
     "tdmap_last_error",
 )
@@ -108,6 +109,16 @@ def tdmap_map_blocks(lambda0: int, count: int, ij: int, stream: int) -> None:
 def tdmap_map_blocks_nodiag(lambda0: int, count: int, ij: int, stream: int) -> None:
     _check(_load().tdmap_map_blocks_nodiag(lambda0, count, ij, stream),
            "tdmap_map_blocks_nodiag")
+
+
+def tdmap_stream_fill(buf: int, n: int, value: float, stream: int) -> None:
+    _check(_load().tdmap_stream_fill(buf, n, value, stream), "tdmap_stream_fill")
+
+
+def stream_fill(buf, value: float = 0.0):
+    """Write-stream reference: buf (a 16-byte aligned float32 CUDA tensor) := value."""
+    tdmap_stream_fill(buf.data_ptr() if buf.numel() else 0, buf.numel(), value, _stream())
+    return buf
 
 
 def tdmap_edm(X: int, N: int, d: int, ldx: int, D: int, ldd: int, layout: int,

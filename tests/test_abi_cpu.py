@@ -93,6 +93,10 @@ def test_validation_rejects_before_launch(lib):
     assert L.tdmap_map_blocks_nodiag(0, 10, None, None) == tdmap.ERR_INVALID
     assert L.tdmap_map_blocks_nodiag((1 << 32) - 5, 6, 8, None) == tdmap.ERR_UNSUPPORTED
     assert L.tdmap_map_blocks_nodiag(5, 0, None, None) == tdmap.OK
+    # the write-stream fill wants a 16-byte aligned buffer
+    assert L.tdmap_stream_fill(None, 16, ctypes.c_float(1.0), None) == tdmap.ERR_INVALID
+    assert L.tdmap_stream_fill(8, 16, ctypes.c_float(1.0), None) == tdmap.ERR_INVALID
+    assert L.tdmap_stream_fill(None, 0, ctypes.c_float(1.0), None) == tdmap.OK
     # the instrumented count needs a paper-style rho
     assert L.tdmap_count_waste(0, 100, 64, 8, None) == tdmap.ERR_UNSUPPORTED
     assert L.tdmap_count_waste(0, 100, 16, None, None) == tdmap.ERR_INVALID

@@ -112,6 +112,20 @@ def test_map_blocks_whole_32bit_range_by_succession():
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 1023, 1 << 20, (1 << 20) + 3])
+def test_stream_fill_writes_exactly_n(n):
+    # the write-stream reference used by the roofline: n floats, the tail
+    # past the last 16-byte chunk included, nothing beyond
+    _require_gpu()
+    guard = 16
+    buf = torch.full((n + guard,), -1.0, dtype=torch.float32, device="cuda")
+    tdmap.stream_fill(buf[:n], 2.5)
+    torch.cuda.synchronize()
+    h = buf.cpu().numpy()
+    assert np.all(h[:n] == 2.5)
+    assert np.all(h[n:] == -1.0)
+
+
 # --------------------------------------------------------------------------
 # EDM, paper-style launches
 # --------------------------------------------------------------------------
