@@ -39,55 +39,68 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// Sum over the 16 lanes of a DPP row (lanes 16r .. 16r + 15); every lane of
-// the row receives the sum.
-__device__ __forceinline__ float row16_sum(float v) {
+// Lanes per row group in the TS = 64 / 128 tiles (16 measured faster than 8:
+// 8 halves the reduction moves per cell but needs three waves per SIMD's
+// worth of registers at TS = 128).
+constexpr int kBwdLanesPerRow = 16;
+
+// Sum over the LPR lanes of a row group (LPR = 8 or 16 consecutive lanes);
+// every lane of the group receives the sum.
+template <int LPR>
+__device__ __forceinline__ float group_sum(float v) {
   v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
   v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
   v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
-  v += dpp_move<0x140, 0xF>(v);  // row_mirror
+  if constexpr (LPR == 16) v += dpp_move<0x140, 0xF>(v);  // row_mirror
   return v;
 }
 
-// The steps of one wave's tile quarter (rows rq0 .. rq0 + H - 1 of the tile,
-// the columns of cbase): dD of step s holds rows rq0 + 16 s + 4 rg + p and
-// columns cbase + 16 q; cells outside the strict lower triangle or past N
-// read 0 (edge and diagonal tiles only).  Row sums go to rowp, column sums
-// accumulate in cacc.
-template <int TS, int D, int LAYOUT, bool INTERIOR>
-__device__ __forceinline__ void bwd_quarter_steps(const BwdArgs &a, const float *xs, float *rowp,
-                                                  const float (&xj)[TS / 32][D],
-                                                  const bool (&jok)[TS / 32],
-                                                  float (&cacc)[TS / 32][D], int64_t row0,
-                                                  int64_t cbase, int rq0, int rg, int cg,
-                                                  bool diag) {
-  constexpr int Q = TS / 32;
-  constexpr int STEPS = TS / 32;
+// Lane layout of a wave's H x H tile quarter: LPR lanes per row group,
+// RG = 64 / LPR row groups; lane l = LPR rg + cg owns columns cg + LPR q
+// (q < Q = H / LPR) and, in 16-row step s, rows rq0 + 16 s + P rg + p
+// (p < P = 16 / RG).
+template <int TS, int LPR>
+struct BwdLayout {
+  static constexpr int H = TS / 2;
+  static constexpr int RG = 64 / LPR;
+  static constexpr int Q = H / LPR;
+  static constexpr int P = 16 / RG;
+  static constexpr int STEPS = H / 16;
+};
+
+template <int TS, int LPR, int D, int LAYOUT, bool INTERIOR>
+__device__ __forceinline__ void bwd_quarter_steps(
+    const BwdArgs &a, const float *xs, float *rowp, const float (&xj)[BwdLayout<TS, LPR>::Q][D],
+    const bool (&jok)[BwdLayout<TS, LPR>::Q], float (&cacc)[BwdLayout<TS, LPR>::Q][D],
+    int64_t row0, int64_t cbase, int rq0, int rg, int cg, bool diag) {
+  using L = BwdLayout<TS, LPR>;
+  constexpr int Q = L::Q;
+  constexpr int P = L::P;
   const int64_t N = a.N;
-  auto load_step = [&](int s, float (&g)[4][Q]) {
+  auto load_step = [&](int s, float (&g)[P][Q]) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int64_t i = row0 + rq0 + 16 * s + 4 * rg + p;
+    for (int p = 0; p < P; ++p) {
+      const int64_t i = row0 + rq0 + 16 * s + P * rg + p;
       const uint64_t base = out_index<LAYOUT>((uint64_t)i, (uint64_t)cbase, a.ldd);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         if constexpr (INTERIOR) {
-          g[p][q] = a.dD[base + 16 * q];
+          g[p][q] = a.dD[base + LPR * q];
         } else {
-          const int64_t j = cbase + 16 * q;
+          const int64_t j = cbase + LPR * q;
           const bool ok = i < N && jok[q] && (!diag || j < i);
-          g[p][q] = ok ? a.dD[base + 16 * q] : 0.0f;
+          g[p][q] = ok ? a.dD[base + LPR * q] : 0.0f;
         }
       }
     }
   };
 #pragma unroll 1
-  for (int s = 0; s < STEPS; ++s) {
-    float g[4][Q];
+  for (int s = 0; s < L::STEPS; ++s) {
+    float g[P][Q];
     load_step(s, g);
-    const int rl = rq0 + 16 * s + 4 * rg;  // tile-local row of p = 0
+    const int rl = rq0 + 16 * s + P * rg;  // tile-local row of p = 0
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < P; ++p) {
       float xi[D], rs[D];
 #pragma unroll
       for (int k = 0; k < D; ++k) {
@@ -112,8 +125,8 @@ __device__ __forceinline__ void bwd_quarter_steps(const BwdArgs &a, const float 
         }
       }
 #pragma unroll
-      for (int k = 0; k < D; ++k) rs[k] = row16_sum(rs[k]);
-      if (cg == 15) {
+      for (int k = 0; k < D; ++k) rs[k] = group_sum<LPR>(rs[k]);
+      if (cg == LPR - 1) {
 #pragma unroll
         for (int k = 0; k < D; ++k) rowp[(rl + p) * D + k] = rs[k];
       }
@@ -123,20 +136,23 @@ __device__ __forceinline__ void bwd_quarter_steps(const BwdArgs &a, const float 
 
 // TS = 64 or 128.  The four waves split the tile into 2 x 2 quarters of
 // H = TS/2 rows and columns; wave w takes row half w >> 1 and column half
-// w & 1.  Inside a wave, lane l = 16 rg + cg owns columns cg + 16q
-// (q < Q = H/16) of its column half, so one load instruction reads 64
-// consecutive bytes of four rows, and rows 4 rg .. 4 rg + 3 of each 16-row
-// step.  A lane thus works on a 4 x Q block of cells per step: the row sums
-// of its four rows are reduced over only the 16 lanes of its DPP row
-// (full-rate moves, no broadcasts), and the column sums stay in registers
-// for the whole tile and are reduced over the four row groups once at the
-// end.  A step's 4 x Q loads are issued together before its arithmetic; the
-// next step's are not prefetched, which keeps the register count at four
-// waves per SIMD (measured faster than prefetching at three).
+// w & 1.  Inside a wave, lane l = LPR rg + cg owns columns cg + LPR q
+// (q < Q = H/LPR) of its column half, so one load instruction reads LPR
+// consecutive cells of each of RG = 64/LPR rows, and rows P rg .. P rg + P - 1
+// (P = 16/RG) of each 16-row step.  A lane thus works on a P x Q block of
+// cells per step: the row sums of its rows are reduced over only the LPR
+// lanes of its row group (full-rate DPP moves, no broadcasts), and the
+// column sums stay in registers for the whole tile and are reduced over the
+// row groups once at the end.  A step's P x Q loads are issued together
+// before its arithmetic; the next step's are not prefetched, which keeps
+// the register count at four waves per SIMD (measured faster than
+// prefetching at three).
 template <int TS, int D, int LAYOUT, bool DET>
 __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
-  constexpr int H = TS / 2;
-  constexpr int Q = H / 16;      // columns per lane
+  constexpr int LPR = kBwdLanesPerRow;
+  using L = BwdLayout<TS, LPR>;
+  constexpr int H = L::H;
+  constexpr int Q = L::Q;
   const uint32_t lam = lam0 + xcd_contiguous(blockIdx.x, gridDim.x);
   uint32_t I, J;
   g_lambda(lam, I, J);
@@ -145,8 +161,8 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
   const int l = t & 63;
   const int ch = w & 1;
   const int rh = w >> 1;
-  const int rg = l >> 4;
-  const int cg = l & 15;
+  const int rg = l / LPR;
+  const int cg = l % LPR;
   const int64_t N = a.N;
   const int64_t row0 = (int64_t)I * TS;
   const int64_t col0 = (int64_t)J * TS;
@@ -165,7 +181,7 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
   bool jok[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int64_t j = cbase + 16 * q;
+    const int64_t j = cbase + LPR * q;
     jok[q] = j < N;
 #pragma unroll
     for (int k = 0; k < D; ++k) xj[q][k] = jok[q] ? a.X[j * a.ldx + k] : 0.0f;
@@ -179,26 +195,26 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
   __syncthreads();
   const bool diag = I == J;
   if ((J < I) && (row0 + TS <= N))
-    bwd_quarter_steps<TS, D, LAYOUT, true>(a, xs, rowp[ch], xj, jok, cacc, row0, cbase, H * rh, rg,
-                                            cg, false);
+    bwd_quarter_steps<TS, LPR, D, LAYOUT, true>(a, xs, rowp[ch], xj, jok, cacc, row0, cbase,
+                                                 H * rh, rg, cg, false);
   else
-    bwd_quarter_steps<TS, D, LAYOUT, false>(a, xs, rowp[ch], xj, jok, cacc, row0, cbase, H * rh,
-                                             rg, cg, diag);
-  // column sums over the four row groups (lanes cg, cg + 16, cg + 32, cg + 48)
+    bwd_quarter_steps<TS, LPR, D, LAYOUT, false>(a, xs, rowp[ch], xj, jok, cacc, row0, cbase,
+                                                  H * rh, rg, cg, diag);
+  // column sums over the row groups (lanes cg + LPR rg)
 #pragma unroll
   for (int q = 0; q < Q; ++q)
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       float v = cacc[q][k];
-      v += __shfl_xor(v, 16, 64);
-      v += __shfl_xor(v, 32, 64);
+#pragma unroll
+      for (int m = LPR; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
       cacc[q][k] = v;
     }
   if (rg == 0) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-      for (int k = 0; k < D; ++k) colp[rh][(H * ch + cg + 16 * q) * D + k] = cacc[q][k];
+      for (int k = 0; k < D; ++k) colp[rh][(H * ch + cg + LPR * q) * D + k] = cacc[q][k];
   }
   __syncthreads();
 
