@@ -14,9 +14,15 @@
 // Full-layout stores are non-temporal (the output is written once and not
 // re-read); packed-layout stores are plain (see put below).
 //
-// LTM launches exactly n(n+1)/2 work-groups, tile (I, J) = g(lambda).  BB
-// launches n x n and returns at once above the diagonal (Sec. III-B), with
-// the same tile body, which makes the two directly comparable.
+// LTM launches exactly n(n+1)/2 work-groups, tile (I, J) = g(lambda) with
+// lambda remapped so that every XCD owns one contiguous range of it
+// (xcd_contiguous in device.h).  BB launches n x n and returns at once above
+// the diagonal (Sec. III-B), with the same tile body, which makes the two
+// directly comparable.
+//
+// Full layout, TS = 256, 16-byte aligned output: edm_tile256_kernel below
+// (no LDS, row points through the scalar cache).  Every other case:
+// edm_tile_kernel.
 #include "device.h"
 #include "kernels.h"
 
