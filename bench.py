@@ -38,12 +38,15 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the sources the EDM kernel is built from; a stored HBM
-    traffic figure is only reported while it matches."""
+    """Hash of the code the EDM kernel is built from (line comments and
+    whitespace removed, so editing a comment keeps it); a stored HBM traffic
+    figure is only reported while it matches."""
+    import re
     h = hashlib.sha256()
     for f in ("device.h", "tiled.hip"):
-        with open(os.path.join(ROOT, "paper_1308_1419_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1308_1419_amd", "csrc", f)) as fh:
+            code = re.sub(r"//[^\n]*", "", fh.read())
+        h.update("".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 
