@@ -155,10 +155,23 @@ def row_stress(torch, tdmap, synth):
         _ = (r * r).sum()
         tdmap.edm_backward(Xd, 2.0 * r, rho=0, deterministic=True, out=dX, workspace=ws)
     t_step = _med_ms(full_step, 20)
+    # fused: loss and gradient in one pass over delta (D never stored)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    ws_s = torch.empty(tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, 3, 0, 0, 1),
+                       dtype=torch.uint8, device="cuda")
+    tdmap.stress_backward(Xd, delta, rho=0, out=dX, loss=loss, workspace=ws_s)
+    tdmap.stress_backward(Xd, delta, rho=0, deterministic=False, out=dX, loss=loss)
+    t_sd = _med_ms(lambda: tdmap.stress_backward(Xd, delta, rho=0, out=dX, loss=loss,
+                                                 workspace=ws_s), 20)
+    t_sa = _med_ms(lambda: tdmap.stress_backward(Xd, delta, rho=0, deterministic=False,
+                                                 out=dX, loss=loss), 20)
     bwd_bytes = 4 * pairs
     return {"N": N, "pairs": pairs, "fwd_us": t_f * 1e3, "bwd_det_us": t_b * 1e3,
             "bwd_atomic_us": t_ba * 1e3, "fwd_bwd_pairs_per_s": pairs / ((t_f + t_b) * 1e-3),
             "step_with_torch_loss_us": t_step * 1e3,
+            "fused_stress_det_us": t_sd * 1e3, "fused_stress_atomic_us": t_sa * 1e3,
+            "fused_stress_hbm_frac": 4 * pairs / (t_sd * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "fused_rho": tdmap.tdmap_tuned_rho(tdmap.OP_STRESS, 0, 0, 3, N),
             "fwd_hbm_frac": 4 * pairs / (t_f * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "bwd_hbm_frac": bwd_bytes / (t_b * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "fwd_rho": tdmap.tdmap_tuned_rho(tdmap.OP_EDM, tdmap.LTM, tdmap.PACKED, 3, N),

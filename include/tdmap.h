@@ -77,7 +77,12 @@ typedef enum {
                              instead of 2^-8 |x| */
 } tdmap_precision;
 
-typedef enum { TDMAP_OP_EDM = 0, TDMAP_OP_BACKWARD = 1, TDMAP_OP_BATCHED = 2 } tdmap_op;
+typedef enum {
+  TDMAP_OP_EDM = 0,
+  TDMAP_OP_BACKWARD = 1,
+  TDMAP_OP_BATCHED = 2,
+  TDMAP_OP_STRESS = 3
+} tdmap_op;
 
 /*
  * g(lambda) over a range of block indices (Sec. II-A, Eq. (2); the row is
@@ -181,6 +186,34 @@ int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx,
                        void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * Stress loss and its gradient in one pass over the targets:
+ *   L = sum_{j<i} (D_ij - delta_ij)^2,
+ *   dX = the gradient above with dD_ij = 2 (D_ij - delta_ij),
+ * D being the EDM of X (Sec. IV, Eq. (17)) computed inside the tiles and
+ * never stored.  The tiles are enumerated by g(lambda) as in the forward
+ * map.  This operation is not in the paper: it is the fitting objective of
+ * metric multidimensional scaling over the triangle the paper maps.
+ *   X      device, N x d FP32, pitch ldx.
+ *   delta  device, targets in `layout` (pitch ldd); diagonal cells and the
+ *          upper triangle of the full layout are not read into the sum.
+ *   dX     device, N x d FP32, row pitch d, overwritten.
+ *   loss   device, one FP32, overwritten with L (0 when N <= 1).
+ *   rho    tile edge: 0 (autotuned), 64 or 128.
+ *   deterministic  1: per-tile partial gradients and losses in the
+ *          workspace, reduced in a fixed order (bitwise reproducible);
+ *          0: atomics (no workspace).
+ *   workspace  device, tdmap_workspace_size(TDMAP_OP_STRESS, N, d, 0, rho,
+ *          deterministic) bytes (0 when deterministic = 0).
+ * d must be 1..4.  Errors as for tdmap_edm_backward; `loss` must be
+ * non-NULL.
+ */
+int tdmap_stress_backward(const float *X, int64_t N, int32_t d, int64_t ldx,
+                          const float *delta, int64_t ldd, int32_t layout,
+                          float *dX, float *loss, int32_t rho,
+                          int32_t deterministic, void *workspace,
+                          size_t ws_bytes, void *stream);
+
+/*
  * Many independent EDMs in one persistent launch (not in the paper; each
  * set is the EDM of Sec. IV on its own points).  Set s owns points
  * X_cat[point_off[s] .. point_off[s+1]) and writes its packed triangle at
@@ -209,7 +242,7 @@ int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets,
 
 /* Bytes of device workspace an operation needs (0 if none).  `flags` is the
  * precision for TDMAP_OP_EDM, `deterministic` for TDMAP_OP_BACKWARD and
- * unused for TDMAP_OP_BATCHED.  Pure host arithmetic. */
+ * TDMAP_OP_STRESS, and unused for TDMAP_OP_BATCHED.  Pure host arithmetic. */
 size_t tdmap_workspace_size(int32_t op, int64_t N, int32_t d, int32_t num_sets,
                             int32_t rho, int32_t flags);
 

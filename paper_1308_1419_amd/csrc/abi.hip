@@ -258,6 +258,13 @@ size_t tdmap_workspace_size(int32_t op, int64_t N, int32_t d, int32_t num_sets, 
                          tdmap::backward_workspace_bytes(N, d, 256)});
       if (rho != 64 && rho != 128 && rho != 256) return 0;
       return tdmap::backward_workspace_bytes(N, d, rho);
+    case TDMAP_OP_STRESS:
+      if (!flags || d > 4) return 0;
+      if (rho == 0)
+        return std::max(tdmap::stress_workspace_bytes(N, d, 64),
+                        tdmap::stress_workspace_bytes(N, d, 128));
+      if (rho != 64 && rho != 128) return 0;
+      return tdmap::stress_workspace_bytes(N, d, rho);
     case TDMAP_OP_BATCHED:
       if (num_sets < 0) return 0;
       return (size_t)(num_sets + 1) * sizeof(uint64_t);
@@ -364,6 +371,48 @@ int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx, const 
     }
   }
   TD_HIP(tdmap::launch_backward(ts, a), "tdmap_edm_backward");
+  return TDMAP_OK;
+}
+
+int tdmap_stress_backward(const float *X, int64_t N, int32_t d, int64_t ldx, const float *delta,
+                          int64_t ldd, int32_t layout, float *dX, float *loss, int32_t rho,
+                          int32_t deterministic, void *workspace, size_t ws_bytes,
+                          void *stream) {
+  int st = validate_edm_common(X, N, d, ldx, delta, ldd, layout);
+  if (st != TDMAP_OK) return st;
+  if (loss == nullptr || (N > 0 && dX == nullptr)) return TDMAP_ERR_INVALID;
+  if (rho != 0 && rho != 64 && rho != 128) return TDMAP_ERR_INVALID;
+  if (d > 4) return TDMAP_ERR_UNSUPPORTED;
+  const uint64_t nb = ceil_div((uint64_t)N, rho ? (uint64_t)rho : 64);
+  if (tri(nb) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
+  const bool det = deterministic != 0;
+  if (det && N > 0) {
+    const size_t need = tdmap_workspace_size(TDMAP_OP_STRESS, N, d, 0, rho, 1);
+    if (workspace == nullptr || ws_bytes < need) return TDMAP_ERR_WORKSPACE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  tdmap::BwdArgs a{X, N, d, ldx, delta, ldd, layout, dX, nullptr, s};
+  a.loss = loss;
+  auto run = [&](int c) {
+    if (det) {
+      // gradient partials of T tiles, then the T loss partials
+      const uint64_t nbc = ceil_div((uint64_t)N, (uint64_t)c);
+      a.ws = reinterpret_cast<float *>(workspace);
+      a.ws_loss = a.ws + tri(nbc) * 2 * (uint64_t)c * (uint64_t)d;
+    }
+    return tdmap::launch_stress(c, a);
+  };
+  int ts = rho;
+  if (ts == 0 && N > 0) {
+    const TuneKey key(TDMAP_OP_STRESS, 0, 0, d, size_bucket(N));
+    ts = tuned_lookup(key);
+    if (ts == 0) {
+      ts = autotune({64, 128}, s, run, &st);
+      if (st != TDMAP_OK) return st;
+      tuned_store(key, ts);
+    }
+  }
+  TD_HIP(run(ts ? ts : 64), "tdmap_stress_backward");
   return TDMAP_OK;
 }
 

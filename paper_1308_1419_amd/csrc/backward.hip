@@ -68,16 +68,20 @@ struct BwdLayout {
   static constexpr int STEPS = H / 16;
 };
 
-template <int TS, int LPR, int D, int LAYOUT, bool INTERIOR>
+// STRESS: the loaded values are the targets delta_ij rather than dL/dD_ij;
+// each cell then takes e = D_ij - delta_ij, adds e^2 to lacc and uses
+// dL/dD_ij = 2 e (cells outside the strict lower triangle contribute
+// nothing to either).
+template <int TS, int LPR, int D, int LAYOUT, bool INTERIOR, bool STRESS>
 __device__ __forceinline__ void bwd_quarter_steps(
     const BwdArgs &a, const float *xs, float *rowp, const float (&xj)[BwdLayout<TS, LPR>::Q][D],
     const bool (&jok)[BwdLayout<TS, LPR>::Q], float (&cacc)[BwdLayout<TS, LPR>::Q][D],
-    int64_t row0, int64_t cbase, int rq0, int rg, int cg, bool diag) {
+    int64_t row0, int64_t cbase, int rq0, int rg, int cg, bool diag, float &lacc) {
   using L = BwdLayout<TS, LPR>;
   constexpr int Q = L::Q;
   constexpr int P = L::P;
   const int64_t N = a.N;
-  auto load_step = [&](int s, float (&g)[P][Q]) {
+  auto load_step = [&](int s, float (&g)[P][Q], bool (&okm)[P][Q]) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const int64_t i = row0 + rq0 + 16 * s + P * rg + p;
@@ -86,10 +90,12 @@ __device__ __forceinline__ void bwd_quarter_steps(
       for (int q = 0; q < Q; ++q) {
         if constexpr (INTERIOR) {
           g[p][q] = a.dD[base + LPR * q];
+          okm[p][q] = true;
         } else {
           const int64_t j = cbase + LPR * q;
           const bool ok = i < N && jok[q] && (!diag || j < i);
           g[p][q] = ok ? a.dD[base + LPR * q] : 0.0f;
+          okm[p][q] = ok;
         }
       }
     }
@@ -97,7 +103,8 @@ __device__ __forceinline__ void bwd_quarter_steps(
 #pragma unroll 1
   for (int s = 0; s < L::STEPS; ++s) {
     float g[P][Q];
-    load_step(s, g);
+    bool okm[P][Q];
+    load_step(s, g, okm);
     const int rl = rq0 + 16 * s + P * rg;  // tile-local row of p = 0
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -116,8 +123,19 @@ __device__ __forceinline__ void bwd_quarter_steps(
           diff[k] = xi[k] - xj[q][k];
           s2 = __builtin_fmaf(diff[k], diff[k], s2);
         }
-        // g is 0 for every cell outside the strict lower triangle
-        const float cc = s2 > 0.0f ? g[p][q] * __builtin_amdgcn_rsqf(s2) : 0.0f;
+        float cc;
+        if constexpr (STRESS) {
+          // D = s2 rsq(s2) (0 at coincident points, where the gradient
+          // term is 0 as well)
+          const float r = s2 > 0.0f ? __builtin_amdgcn_rsqf(s2) : 0.0f;
+          const float e = s2 * r - g[p][q];
+          const bool ok = INTERIOR || okm[p][q];
+          lacc = ok ? __builtin_fmaf(e, e, lacc) : lacc;
+          cc = ok ? 2.0f * e * r : 0.0f;
+        } else {
+          // g is 0 for every cell outside the strict lower triangle
+          cc = s2 > 0.0f ? g[p][q] * __builtin_amdgcn_rsqf(s2) : 0.0f;
+        }
 #pragma unroll
         for (int k = 0; k < D; ++k) {
           rs[k] = __builtin_fmaf(cc, diff[k], rs[k]);
@@ -147,7 +165,7 @@ __device__ __forceinline__ void bwd_quarter_steps(
 // before its arithmetic; the next step's are not prefetched, which keeps
 // the register count at four waves per SIMD (measured faster than
 // prefetching at three).
-template <int TS, int D, int LAYOUT, bool DET>
+template <int TS, int D, int LAYOUT, bool DET, bool STRESS = false>
 __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
   constexpr int LPR = kBwdLanesPerRow;
   using L = BwdLayout<TS, LPR>;
@@ -194,12 +212,18 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
 
   __syncthreads();
   const bool diag = I == J;
+  float lacc = 0.0f;
   if ((J < I) && (row0 + TS <= N))
-    bwd_quarter_steps<TS, LPR, D, LAYOUT, true>(a, xs, rowp[ch], xj, jok, cacc, row0, cbase,
-                                                 H * rh, rg, cg, false);
+    bwd_quarter_steps<TS, LPR, D, LAYOUT, true, STRESS>(a, xs, rowp[ch], xj, jok, cacc, row0,
+                                                         cbase, H * rh, rg, cg, false, lacc);
   else
-    bwd_quarter_steps<TS, LPR, D, LAYOUT, false>(a, xs, rowp[ch], xj, jok, cacc, row0, cbase,
-                                                  H * rh, rg, cg, diag);
+    bwd_quarter_steps<TS, LPR, D, LAYOUT, false, STRESS>(a, xs, rowp[ch], xj, jok, cacc, row0,
+                                                          cbase, H * rh, rg, cg, diag, lacc);
+  __shared__ float lossp[4];
+  if constexpr (STRESS) {
+    lacc = wave_sum(lacc);
+    if (l == kSumLane) lossp[w] = lacc;
+  }
   // column sums over the row groups (lanes cg + LPR rg)
 #pragma unroll
   for (int q = 0; q < Q; ++q)
@@ -230,6 +254,15 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
       const int k = e - r * D;
       if (row0 + r < N) atomicAdd(&a.dX[(row0 + r) * D + k], rsum);
       if (col0 + r < N) atomicAdd(&a.dX[(col0 + r) * D + k], csum);
+    }
+  }
+  if constexpr (STRESS) {
+    if (t == 0) {
+      const float tl = (lossp[0] + lossp[1]) + (lossp[2] + lossp[3]);
+      if constexpr (DET)
+        a.ws_loss[lam] = tl;
+      else
+        atomicAdd(a.loss, tl);
     }
   }
 }
@@ -462,6 +495,87 @@ static hipError_t launch_bwd_ts(const BwdArgs &a) {
     case 2: return launch_bwd_d<TS, 2>(a);
     case 3: return launch_bwd_d<TS, 3>(a);
     case 4: return launch_bwd_d<TS, 4>(a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Deterministic total of the per-tile losses: one work-group, thread t
+// adds entries t, t + 1024, ... in order, then a fixed tree.
+__global__ __launch_bounds__(1024) void stress_loss_reduce(const float *__restrict__ part,
+                                                           uint64_t count, float *__restrict__ loss) {
+  __shared__ float buf[1024];
+  const int t = threadIdx.x;
+  float acc = 0.0f;
+  for (uint64_t e = t; e < count; e += 1024) acc += part[e];
+  buf[t] = acc;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) buf[t] += buf[t + off];
+    __syncthreads();
+  }
+  if (t == 0) loss[0] = buf[0];
+}
+
+template <int TS, int D, int LAYOUT, bool DET>
+static hipError_t launch_stress_t(const BwdArgs &a) {
+  const uint64_t nb = (uint64_t)((a.N + TS - 1) / TS);
+  const uint64_t T = nb * (nb + 1) / 2;
+  hipError_t e;
+  if (!DET) {
+    if ((e = launch_fill(a.dX, (uint64_t)a.N * D, 0.0f, a.stream)) != hipSuccess) return e;
+    if ((e = launch_fill(a.loss, 1, 0.0f, a.stream)) != hipSuccess) return e;
+  }
+  const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
+  for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
+    const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
+    hipLaunchKernelGGL((edm_bwd_tile<TS, D, LAYOUT, DET, true>), dim3((uint32_t)c), dim3(256), 0,
+                       a.stream, a, (uint32_t)l0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (DET) {
+    hipLaunchKernelGGL((edm_bwd_reduce<TS, D>), dim3((uint32_t)nb), dim3(TS * D), 0, a.stream,
+                       a.ws, a.dX, a.N, (uint32_t)nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(stress_loss_reduce, dim3(1), dim3(1024), 0, a.stream, a.ws_loss, T, a.loss);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int TS, int D>
+static hipError_t launch_stress_d(const BwdArgs &a) {
+  const bool det = a.ws != nullptr;
+  if (a.layout == kLayoutFull)
+    return det ? launch_stress_t<TS, D, kLayoutFull, true>(a) : launch_stress_t<TS, D, kLayoutFull, false>(a);
+  if (a.layout == kLayoutStrict)
+    return det ? launch_stress_t<TS, D, kLayoutStrict, true>(a)
+               : launch_stress_t<TS, D, kLayoutStrict, false>(a);
+  return det ? launch_stress_t<TS, D, kLayoutPacked, true>(a)
+             : launch_stress_t<TS, D, kLayoutPacked, false>(a);
+}
+
+template <int TS>
+static hipError_t launch_stress_ts(const BwdArgs &a) {
+  switch (a.d) {
+    case 1: return launch_stress_d<TS, 1>(a);
+    case 2: return launch_stress_d<TS, 2>(a);
+    case 3: return launch_stress_d<TS, 3>(a);
+    case 4: return launch_stress_d<TS, 4>(a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t stress_workspace_bytes(int64_t N, int d, int ts) {
+  const uint64_t nb = (uint64_t)((N + ts - 1) / ts);
+  const uint64_t T = nb * (nb + 1) / 2;
+  return (size_t)T * (2 * (size_t)ts * (size_t)d + 1) * sizeof(float);
+}
+
+hipError_t launch_stress(int ts, const BwdArgs &a) {
+  if (a.N == 0) return launch_fill(a.loss, 1, 0.0f, a.stream);
+  switch (ts) {
+    case 64: return launch_stress_ts<64>(a);
+    case 128: return launch_stress_ts<128>(a);
     default: return hipErrorInvalidValue;
   }
 }

@@ -54,11 +54,20 @@ struct BwdArgs {
   float *dX;
   float *ws;  // per-tile partial sums (deterministic mode), else nullptr
   hipStream_t stream;
+  // stress mode: dD holds the targets delta, loss receives
+  // L = sum_{j<i} (D_ij - delta_ij)^2 (one float), ws_loss the per-tile
+  // partial losses (deterministic mode)
+  float *loss = nullptr;
+  float *ws_loss = nullptr;
 };
 
 // Backward over g(lambda) tiles of edge ts (64 or 128); d in 1..4.
 size_t backward_workspace_bytes(int64_t N, int d, int ts);
 hipError_t launch_backward(int ts, const BwdArgs &a);
+// Stress loss and its gradient in one pass (ts 64 or 128): the per-tile
+// loss partials follow the dX partials in the workspace.
+size_t stress_workspace_bytes(int64_t N, int d, int ts);
+hipError_t launch_stress(int ts, const BwdArgs &a);
 
 struct BatchArgs {
   const float *X;          // concatenated points, pitch d

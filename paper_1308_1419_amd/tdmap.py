@@ -26,7 +26,7 @@ OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = range(5)
 LTM, BB, UTM, RB, REC = range(5)
 FULL, PACKED, PACKED_STRICT = 0, 1, 2
 FP32, BF16_GRAM, BF16X3_GRAM = 0, 1, 2
-OP_EDM, OP_BACKWARD, OP_BATCHED = 0, 1, 2
+OP_EDM, OP_BACKWARD, OP_BATCHED, OP_STRESS = 0, 1, 2, 3
 
 STRATEGIES = {"ltm": LTM, "bb": BB, "utm": UTM, "rb": RB, "rec": REC}
 LAYOUTS = {"full": FULL, "packed": PACKED, "strict": PACKED_STRICT}
@@ -65,6 +65,8 @@ def _load() -> ctypes.CDLL:
                       ctypes.c_int),
         "tdmap_edm_backward": ([vp, i64, i32, i64, vp, i64, i32, vp, i32, i32, vp, sz, vp],
                                ctypes.c_int),
+        "tdmap_stress_backward": ([vp, i64, i32, i64, vp, i64, i32, vp, vp, i32, i32, vp, sz,
+                                   vp], ctypes.c_int),
         "tdmap_edm_batched": ([vp, i32, i32, vp, vp, vp, i32, vp, sz, vp], ctypes.c_int),
         "tdmap_workspace_size": ([i32, i64, i32, i32, i32, i32], sz),
         "tdmap_waste_counts": ([i32, i64, i32, vp], ctypes.c_int),
@@ -85,7 +87,8 @@ def _load() -> ctypes.CDLL:
 
 
 EXPORTED = (
-    "tdmap_map_blocks", "tdmap_map_blocks_nodiag", "tdmap_edm", "tdmap_edm_backward", "tdmap_edm_batched",
+    "tdmap_map_blocks", "tdmap_map_blocks_nodiag", "tdmap_edm", "tdmap_edm_backward",
+    "tdmap_stress_backward", "tdmap_edm_batched",
     "tdmap_workspace_size", "tdmap_waste_counts", "tdmap_count_waste",
     "tdmap_map_blocks_variant", "tdmap_dummy", "tdmap_stream_fill",
     "tdmap_tuned_rho", "tdmap_autotune_reset", "tdmap_status_string",
@@ -134,6 +137,14 @@ def tdmap_edm_backward(X: int, N: int, d: int, ldx: int, dD: int, ldd: int,
     _check(_load().tdmap_edm_backward(X, N, d, ldx, dD, ldd, layout, dX, rho,
                                       deterministic, workspace, ws_bytes, stream),
            "tdmap_edm_backward")
+
+
+def tdmap_stress_backward(X: int, N: int, d: int, ldx: int, delta: int, ldd: int,
+                          layout: int, dX: int, loss: int, rho: int, deterministic: int,
+                          workspace: int, ws_bytes: int, stream: int) -> None:
+    _check(_load().tdmap_stress_backward(X, N, d, ldx, delta, ldd, layout, dX, loss, rho,
+                                         deterministic, workspace, ws_bytes, stream),
+           "tdmap_stress_backward")
 
 
 def tdmap_edm_batched(X_cat: int, d: int, num_sets: int, point_off: int, out_off: int,
@@ -299,6 +310,34 @@ def edm_backward(X, dD, layout: str = "packed", rho: int = 0, deterministic: boo
     tdmap_edm_backward(X.data_ptr(), N, d, X.stride(0), dD.data_ptr(), ldd, lay,
                        out.data_ptr(), rho, det, ws_ptr, ws_len, _stream())
     return out
+
+
+def stress_backward(X, delta, layout: str = "packed", rho: int = 0,
+                    deterministic: bool = True, ldd: Optional[int] = None, out=None,
+                    loss=None, workspace=None):
+    """(loss, dX) of L = sum_{j<i} (D_ij - delta_ij)^2 in one pass (see
+    tdmap_stress_backward); ``loss`` is a one-element CUDA tensor."""
+    torch = _torch()
+    X = _points(X)
+    N, d = X.shape
+    lay = LAYOUTS[layout]
+    if out is None:
+        out = torch.empty((N, d), dtype=torch.float32, device=X.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    if ldd is None:
+        ldd = delta.stride(0) if lay == FULL else 0
+    det = 1 if deterministic else 0
+    ws_bytes = tdmap_workspace_size(OP_STRESS, N, d, 0, rho, det)
+    if ws_bytes and workspace is None:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=X.device)
+    ws_ptr = workspace.data_ptr() if workspace is not None else 0
+    ws_len = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    delta_ptr = delta.data_ptr() if delta.numel() else 0
+    tdmap_stress_backward(X.data_ptr(), N, d, X.stride(0), delta_ptr, ldd, lay,
+                          out.data_ptr(), loss.data_ptr(), rho, det, ws_ptr, ws_len,
+                          _stream())
+    return loss, out
 
 
 def edm_batched(X_cat, point_off, out_off, rho: int = 0, out=None, workspace=None):

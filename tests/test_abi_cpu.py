@@ -122,6 +122,42 @@ def test_gram_workspace_sizes(lib):
         == tdmap.ERR_INVALID
 
 
+def test_stress_validation_and_workspace(lib):
+    L = tdmap._load()
+    N, d = 1000, 3
+    # per tile: 2 ts d gradient partials and one loss partial
+    for ts in (64, 128):
+        nb = -(-N // ts)
+        T = nb * (nb + 1) // 2
+        assert tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, ts, 1) == \
+            T * (2 * ts * d + 1) * 4
+    assert tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, 0, 1) == max(
+        tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, ts, 1) for ts in (64, 128))
+    assert tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, 64, 0) == 0
+    assert tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, 256, 1) == 0
+    assert tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, 5, 0, 64, 1) == 0
+    P = tdmap.PACKED
+    # NULL loss / dX / delta, bad rho, d > 4, a workspace too small
+    assert L.tdmap_stress_backward(8, N, d, d, 16, 0, P, 8, None, 64, 0, None, 0, None) \
+        == tdmap.ERR_INVALID
+    assert L.tdmap_stress_backward(8, N, d, d, 16, 0, P, None, 8, 64, 0, None, 0, None) \
+        == tdmap.ERR_INVALID
+    assert L.tdmap_stress_backward(8, N, d, d, None, 0, P, 8, 8, 64, 0, None, 0, None) \
+        == tdmap.ERR_INVALID
+    assert L.tdmap_stress_backward(8, N, d, d, 16, 0, P, 8, 8, 256, 0, None, 0, None) \
+        == tdmap.ERR_INVALID
+    assert L.tdmap_stress_backward(8, N, 5, 5, 16, 0, P, 8, 8, 64, 0, None, 0, None) \
+        == tdmap.ERR_UNSUPPORTED
+    need = tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, 64, 1)
+    assert L.tdmap_stress_backward(8, N, d, d, 16, 0, P, 8, 8, 64, 1, 16, need - 1, None) \
+        == tdmap.ERR_WORKSPACE
+    need0 = tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, 0, 1)
+    assert L.tdmap_stress_backward(8, N, d, d, 16, 0, P, 8, 8, 0, 1, 16, need0 - 1, None) \
+        == tdmap.ERR_WORKSPACE  # rho = 0 needs room for either tile edge
+    assert L.tdmap_stress_backward(8, N, d, d, 16, N - 1, tdmap.FULL, 8, 8, 64, 0, None, 0,
+                                   None) == tdmap.ERR_INVALID
+
+
 def test_fp32_needs_no_workspace(lib):
     for rho in (0, 8, 16, 32, 64, 128, 256):
         assert tdmap.tdmap_workspace_size(tdmap.OP_EDM, 30000, 3, 0, rho, tdmap.FP32) == 0

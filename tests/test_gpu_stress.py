@@ -1,0 +1,223 @@
+"""GPU parity of the fused stress loss and gradient (tdmap_stress_backward)
+against the FP64 oracle.
+
+L = sum_{j<i} (D_ij - delta_ij)^2 with D the EDM of X (Sec. IV, Eq. (17)),
+dX its gradient.  Both sides take the same FP32 targets delta.
+
+Loss tolerance, from the arithmetic: a kernel distance carries at most about
+(d/2 + 2) u D of rounding (the d products of the squared norm, the
+reciprocal square root, the product), so each residual e = D - delta is off
+by at most 4 u D + u |e| for d <= 4, and e^2 by 2 |e| of that; the partial
+sums add at most (depth) u L, depth being the longest chain of FP32
+additions a term passes through (the cells of one lane, the wave and tile
+trees, then T / 1024 tiles in order and a 1024-wide tree; in atomic mode
+the T tile totals in any order).  Hence
+    |L_gpu - L_64| <= 10 u sum |e| D + (depth + 4) u L_64,   u = 2^-24.
+Gradient: the tolerance of the EDM gradient,
+    max |dX_gpu - dX_64| <= 1e-4 max |dX_64|,
+    ||dX_gpu - dX_64||_2 <= 1e-5 ||dX_64||_2.
+"""
+import numpy as np
+import pytest
+
+from oracle import edm as oedm
+from oracle import native
+from paper_1308_1419_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1308_1419_amd import tdmap  # noqa: E402
+
+U = 2.0 ** -24
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test collected on a machine without a GPU")
+
+
+def _check_grad(got, ref, where=""):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.abs(ref).max()
+    if scale == 0:
+        assert np.all(got == 0), where
+        return
+    err = np.abs(got - ref)
+    assert err.max() <= 1e-4 * scale, f"{where}: max err {err.max()} scale {scale}"
+    assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref), where
+
+
+def _loss_bound(D64, delta, L64, N, ts, det):
+    offdiag = _offdiag_mask(N)
+    e = np.where(offdiag, D64 - delta.astype(np.float64), 0.0)
+    nb = -(-N // ts)
+    T = nb * (nb + 1) // 2
+    depth = (ts * ts // 256 + 6 + 2 + -(-T // 1024) + 10) if det else (ts * ts // 256 + 8 + T)
+    return 10 * U * float(np.sum(np.abs(e) * D64)) + (depth + 4) * U * L64
+
+
+def _offdiag_mask(N):
+    m = np.ones(oedm.tri(N), dtype=bool)
+    m[[oedm.tri(i) + i for i in range(N)]] = False
+    return m
+
+
+def _strict_from_packed(P, N):
+    return np.concatenate([P[oedm.tri(i): oedm.tri(i) + i] for i in range(N)]) if N > 1 \
+        else np.zeros(0, dtype=P.dtype)
+
+
+def _full_from_packed(P, N, fill=np.nan):
+    F = np.full((N, N), fill, dtype=np.float32)
+    for i in range(N):
+        F[i, : i + 1] = P[oedm.tri(i): oedm.tri(i) + i + 1]
+    return F
+
+
+def _targets(N, d, seed):
+    # delta: the FP64 distances of perturbed points rounded to FP32, with a
+    # deliberately wrong diagonal (it must not enter the loss)
+    X, Xp = synth.stress_inputs(N, d, seed=seed)
+    delta = oedm.edm64_packed(Xp).astype(np.float32)
+    delta[[oedm.tri(i) + i for i in range(N)]] = 7.0
+    return X, delta
+
+
+def _device_targets(delta, N, layout):
+    if layout == "packed":
+        return torch.from_numpy(delta).cuda()
+    if layout == "strict":
+        return torch.from_numpy(_strict_from_packed(delta, N)).cuda()
+    return torch.from_numpy(_full_from_packed(delta, N)).cuda()
+
+
+@pytest.mark.parametrize("layout", ["packed", "strict", "full"])
+@pytest.mark.parametrize("rho", [64, 128, 0])
+@pytest.mark.parametrize("det", [True, False])
+@pytest.mark.parametrize("N,d", [(2, 3), (3, 1), (37, 2), (64, 3), (65, 3), (300, 3),
+                                 (1000, 4), (1100, 3)])
+def test_stress_against_oracle(layout, rho, det, N, d):
+    _require_gpu()
+    X, delta = _targets(N, d, seed=900 + N + d)
+    Xd = torch.from_numpy(X).cuda()
+    loss, dX = tdmap.stress_backward(Xd, _device_targets(delta, N, layout), layout=layout,
+                                     rho=rho, deterministic=det)
+    torch.cuda.synchronize()
+    L64, g64 = oedm.stress_grad64(X, delta)
+    D64 = oedm.edm64_packed(X)
+    ts = rho if rho else 128  # the bound of the larger tile covers both
+    bound = max(_loss_bound(D64, delta, L64, N, ts, det),
+                _loss_bound(D64, delta, L64, N, 64, det))
+    got = float(loss.item())
+    assert abs(got - L64) <= bound, f"L {got} vs {L64}, bound {bound}"
+    _check_grad(dX.cpu().numpy(), g64, f"{layout} N={N} d={d} rho={rho} det={det}")
+
+
+@pytest.mark.parametrize("layout", ["packed", "strict"])
+def test_stress_deterministic_bits_and_workspace_reuse(layout):
+    _require_gpu()
+    N, d = 1300, 3
+    X, delta = _targets(N, d, seed=31)
+    Xd = torch.from_numpy(X).cuda()
+    dd = _device_targets(delta, N, layout)
+    ws = torch.empty(tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, 0, 1),
+                     dtype=torch.uint8, device="cuda")
+    for rho in (64, 128):
+        ws.fill_(0xFF)  # stale partials from another call must not leak in
+        l1, g1 = tdmap.stress_backward(Xd, dd, layout=layout, rho=rho, workspace=ws)
+        l1, g1 = l1.clone(), g1.clone()
+        l2, g2 = tdmap.stress_backward(Xd, dd, layout=layout, rho=rho, workspace=ws)
+        torch.cuda.synchronize()
+        assert torch.equal(l1.view(torch.int32), l2.view(torch.int32))
+        assert torch.equal(g1.view(torch.int32), g2.view(torch.int32))
+
+
+def test_stress_strict_equals_packed_bits():
+    # one per-pair function: the strict targets give the packed result bit for
+    # bit (deterministic mode), the packed diagonal being ignored
+    _require_gpu()
+    N, d = 777, 3
+    X, delta = _targets(N, d, seed=5)
+    Xd = torch.from_numpy(X).cuda()
+    for rho in (64, 128):
+        lp, gp = tdmap.stress_backward(Xd, _device_targets(delta, N, "packed"), rho=rho)
+        ls, gs = tdmap.stress_backward(Xd, _device_targets(delta, N, "strict"), layout="strict",
+                                       rho=rho)
+        lf, gf = tdmap.stress_backward(Xd, _device_targets(delta, N, "full"), layout="full",
+                                       rho=rho)
+        torch.cuda.synchronize()
+        for l_, g_ in ((ls, gs), (lf, gf)):
+            assert torch.equal(lp.view(torch.int32), l_.view(torch.int32))
+            assert torch.equal(gp.view(torch.int32), g_.view(torch.int32))
+
+
+def test_stress_matches_composed_path():
+    # the fused pass against forward + cell gradient + backward on the GPU
+    _require_gpu()
+    N, d = 2000, 3
+    X, delta = _targets(N, d, seed=8)
+    Xd = torch.from_numpy(X).cuda()
+    dl = torch.from_numpy(delta).cuda()
+    loss, dX = tdmap.stress_backward(Xd, dl, rho=0)
+    D = tdmap.edm(Xd, layout="packed", rho=0)
+    r = (D - dl).double()
+    r[torch.tensor([oedm.tri(i) + i for i in range(N)], device="cuda")] = 0.0
+    ref = tdmap.edm_backward(Xd, (2.0 * r).float(), rho=0)
+    torch.cuda.synchronize()
+    assert abs(float(loss.item()) - float((r * r).sum())) <= 1e-5 * float((r * r).sum())
+    _check_grad(dX.cpu().numpy(), ref.cpu().numpy().astype(np.float64), "composed")
+
+
+def test_stress_degenerate_inputs():
+    _require_gpu()
+    loss = torch.full((1,), 5.0, device="cuda")
+    # no points: the loss is 0 and nothing else is touched
+    X0 = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    tdmap.stress_backward(X0, torch.empty(0, device="cuda"), loss=loss)
+    torch.cuda.synchronize()
+    assert float(loss.item()) == 0.0
+    # one point: no pair; strict targets may be empty
+    X1 = torch.from_numpy(synth.uniform_points(1, 3, seed=2)).cuda()
+    for layout, dl in (("packed", torch.full((1,), 3.0, device="cuda")),
+                       ("strict", torch.empty(0, device="cuda"))):
+        for det in (True, False):
+            loss.fill_(5.0)
+            _, g = tdmap.stress_backward(X1, dl, layout=layout, deterministic=det, loss=loss)
+            torch.cuda.synchronize()
+            assert float(loss.item()) == 0.0
+            assert np.all(g.cpu().numpy() == 0.0)
+    # coincident points with zero targets: L = 0 and a zero gradient
+    Xc = torch.zeros((200, 3), dtype=torch.float32, device="cuda")
+    l_, g = tdmap.stress_backward(Xc, torch.zeros(oedm.tri(200), device="cuda"), rho=64)
+    torch.cuda.synchronize()
+    assert float(l_.item()) == 0.0 and np.all(g.cpu().numpy() == 0.0)
+
+
+def test_stress_workload_full_size():
+    # the 20000-point stress workload, fused: the loss against the FP64 sum
+    # over all 2 x 10^8 pairs and the gradient against the FP64 gradient of
+    # the same targets
+    _require_gpu()
+    N = 20000
+    X, Xp = synth.stress_inputs(N, 3, seed=synth.workload_seed(4))
+    delta64 = np.concatenate(native.edm_rows(Xp, range(N)))
+    delta32 = delta64.astype(np.float32)
+    D64 = np.concatenate(native.edm_rows(X, range(N)))
+    off = _offdiag_mask(N)
+    e = np.where(off, D64 - delta32.astype(np.float64), 0.0)
+    L64 = float(np.dot(e, e))
+    g64 = native.edm_backward(X, (2.0 * e).astype(np.float32))
+    Xd = torch.from_numpy(X).cuda()
+    dl = torch.from_numpy(delta32).cuda()
+    for det in (True, False):
+        for rho in (64, 128):
+            loss, dX = tdmap.stress_backward(Xd, dl, rho=rho, deterministic=det)
+            torch.cuda.synchronize()
+            nb = -(-N // rho)
+            T = nb * (nb + 1) // 2
+            depth = (rho * rho // 256 + 18 + -(-T // 1024)) if det else (rho * rho // 256 + 8 + T)
+            bound = 10 * U * float(np.dot(np.abs(e), D64)) + (depth + 4) * U * L64
+            assert abs(float(loss.item()) - L64) <= bound, (det, rho)
+            _check_grad(dX.cpu().numpy(), g64, f"N=20000 det={det} rho={rho}")
