@@ -180,6 +180,19 @@ def test_gradient_invariances(impl):
     assert np.all(np.abs(torque) <= 1e-11 * scale * 120)
 
 
+@pytest.mark.parametrize("N,d", [(2, 1), (40, 3), (301, 4)])
+def test_stress_value_matches_pdist(N, d):
+    # L over the pairs j < i equals the sum over scipy's pair list of
+    # (|x_i - x_j| - |x'_i - x'_j|)^2; a wrong diagonal in delta is ignored
+    X, Xp = synth.stress_inputs(N, d, seed=60 + N)
+    delta = edm.edm64_packed(Xp)
+    delta[[edm.tri(i) + i for i in range(N)]] = 3.5
+    L, _, dD = edm.stress64(X, delta)
+    r = pdist(X.astype(np.float64)) - pdist(Xp.astype(np.float64))
+    assert abs(L - float(np.dot(r, r))) <= 1e-12 * float(np.dot(r, r))
+    assert np.all(dD[[edm.tri(i) + i for i in range(N)]] == 0.0)
+
+
 def test_stress_zero_at_target():
     X = synth.uniform_points(50, 3, seed=2)
     L, dX = edm.stress_grad64(X, edm.edm64_packed(X))
