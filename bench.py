@@ -430,7 +430,7 @@ def main():
     D = torch.empty((N, N), dtype=torch.float32, device="cuda")
     stream_gbs = bytes_alg / (t_stream * 1e-3) / 1e9
     traffic = stored_traffic()
-    kname = (f"edm_tile256_kernel<{d}, false>" if ts_ltm == 256
+    kname = (f"edm_band_kernel<{d}, false, true>" if ts_ltm == 256
              else f"edm_tile_kernel<{ts_ltm}, {d}, 0, true, false>")
     if traffic and not traffic["kernel"].startswith(kname):
         traffic = None  # the counters were taken on another tile kernel
