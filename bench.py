@@ -51,7 +51,7 @@ def kernel_source_hash() -> str:
 
 
 def stored_traffic():
-    path = os.path.join(ROOT, "profiles", "traffic_edm_tile_n30000_d3_full.json")
+    path = os.path.join(ROOT, "profiles", "traffic_edm_band_n30000_d3_full.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:

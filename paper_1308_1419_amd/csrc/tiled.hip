@@ -7,10 +7,10 @@
 //   - the tile's TS row points are staged once in LDS (read back with
 //     broadcast, all lanes of a row share an address);
 //   - each lane keeps its column points in registers;
-//   - with VEC a lane owns four consecutive columns and stores them with one
-//     16-byte store, so a wave writes TS/4-lane runs of 16 bytes: whole
-//     64-byte segments of a row.  Without VEC (packed rows start at any
-//     offset) a lane owns one column and a wave writes 256 contiguous bytes.
+//   - with VEC (full layout) a lane owns four consecutive columns and
+//     stores them with one 16-byte store, so a wave writes TS/4-lane runs of
+//     16 bytes: whole 64-byte segments of a row.  Without VEC a lane owns one
+//     column and a wave writes 256 contiguous bytes.
 // Full-layout stores are non-temporal (the output is written once and not
 // re-read); packed-layout stores are plain (see put below).
 //
@@ -20,9 +20,11 @@
 // the diagonal (Sec. III-B), with the same tile body, which makes the two
 // directly comparable.
 //
-// Full layout, TS = 256, 16-byte aligned output: edm_band_kernel below
-// (the tiles written as 8-row strips, no LDS, row points through the scalar
-// cache).  Every other case: edm_tile_kernel.
+// TS = 256 with a 16-byte aligned output: edm_band_kernel below, which
+// writes each tile as 8-row strips (one strip per work-group, no LDS, row
+// points through the scalar cache; packed rows are realigned to 16-byte
+// chunks).  TS = 64 / 128, and TS = 256 with an unaligned output:
+// edm_tile_kernel.
 #include "device.h"
 #include "kernels.h"
 
@@ -44,8 +46,8 @@ __device__ __forceinline__ void put(T v, T *p) {
     *p = v;
 }
 
-// Interior tile rows in the packed layout with 16-byte stores (TS = 256:
-// one row per wave and pass).  Packed row i starts at R(i) = i(i+1)/2 (or
+// Interior rows of a 256-column segment in the packed layout with 16-byte
+// stores (one row per wave and call).  Packed row i starts at R(i) = i(i+1)/2 (or
 // i(i-1)/2 without the diagonal), so the tile's row segment
 // [col0, col0 + 256) begins s = (R(i) + col0) mod 4 positions past a
 // 16-byte boundary.  Lane l stores the aligned chunk
@@ -58,17 +60,47 @@ __device__ __forceinline__ void put(T v, T *p) {
 // first chunk, lanes 3..5 positions 0..2 of the chunk after the last full
 // one, and each keeps the point it needs for every s.  The neighbouring
 // tiles write the rest of the two shared chunks.
-template <int TS, int D, int LAYOUT>
-__device__ __forceinline__ void packed_vec_rows(const EdmArgs &a, const float *xs, int64_t row0,
-                                                int64_t col0, int lr, float *__restrict__ out) {
-  static_assert(TS == 256, "one tile row per wave");
+template <int D>
+struct PackedWindow {
+  float win[7][D];   // columns col0 + 4l - 3 .. col0 + 4l + 3
+  float edge[3][D];  // the edge lane's point for s = 1, 2, 3
+};
+
+__device__ __forceinline__ float lane_value(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// XV: X is dense (ldx = D) and 16-byte aligned; the window of lane l is
+// then read as 2 D aligned 16-byte chunks (columns col0 + 4l - 4 ..
+// col0 + 4l + 3) and the edge points are taken from the windows of lanes 0
+// and 63 instead of from memory (every lane of the wave must be active).
+template <int D, bool XV = false>
+__device__ __forceinline__ void packed_window(const float *__restrict__ X, int64_t ldx, int64_t col0,
+                                              PackedWindow<D> &w) {
   const int l = threadIdx.x & 63;
-  float win[7][D];
+  const int64_t c0 = col0 + 4 * l - 4;
+  if (XV && c0 >= 0) {
+    const f4 *q = reinterpret_cast<const f4 *>(X + c0 * D);
+    float v[8 * D];
 #pragma unroll
-  for (int o = 0; o < 7; ++o) {
-    const int64_t c = col0 + 4 * l - 3 + o;
+    for (int m = 0; m < 2 * D; ++m) {
+      const f4 t = q[m];
+      v[4 * m] = t.x;
+      v[4 * m + 1] = t.y;
+      v[4 * m + 2] = t.z;
+      v[4 * m + 3] = t.w;
+    }
 #pragma unroll
-    for (int k = 0; k < D; ++k) win[o][k] = c >= 0 ? a.X[c * a.ldx + k] : 0.0f;
+    for (int o = 0; o < 7; ++o)
+#pragma unroll
+      for (int k = 0; k < D; ++k) w.win[o][k] = v[(o + 1) * D + k];
+  } else {
+#pragma unroll
+    for (int o = 0; o < 7; ++o) {
+      const int64_t c = c0 + 1 + o;
+#pragma unroll
+      for (int k = 0; k < D; ++k) w.win[o][k] = c >= 0 ? X[c * ldx + k] : 0.0f;
+    }
   }
   // edge lane e = l (head, l < 3) or l - 3 (tail, 3 <= l < 6); for shift s
   // it owns column col0 + 1 + l - s (head, kept when l + 1 >= s) or
@@ -76,55 +108,76 @@ __device__ __forceinline__ void packed_vec_rows(const EdmArgs &a, const float *x
   // A0 + 1 + l or A0 + 253 + l
   const bool head = l < 3;
   const int e = head ? l : l - 3;
-  float edge[3][D];
+  if constexpr (XV) {
+    // column col0 + 1 + l - s is lane 0's win[4 + l - s] (index 1..5);
+    // column col0 + 256 - s + e is lane 63's win[7 - s + e] (4..6 when kept)
 #pragma unroll
-  for (int s = 1; s <= 3; ++s) {
-    const bool ok = l < 6 && (head ? l + 1 >= s : e < s);
-    const int64_t c = head ? col0 + 1 + l - s : col0 + 256 - s + e;
+    for (int k = 0; k < D; ++k) {
+      float h[6], t[7];
 #pragma unroll
-    for (int k = 0; k < D; ++k) edge[s - 1][k] = ok ? a.X[c * a.ldx + k] : 0.0f;
+      for (int o = 1; o <= 5; ++o) h[o] = lane_value(w.win[o][k], 0);
+#pragma unroll
+      for (int o = 4; o <= 6; ++o) t[o] = lane_value(w.win[o][k], 63);
+#pragma unroll
+      for (int s = 1; s <= 3; ++s) {
+        const int oh = 4 + l - s;
+        const int ot = 7 - s + e;
+        const float hv = oh <= 1 ? h[1] : oh == 2 ? h[2] : oh == 3 ? h[3] : oh == 4 ? h[4] : h[5];
+        const float tv = ot <= 4 ? t[4] : ot == 5 ? t[5] : t[6];
+        const bool ok = l < 6 && (head ? l + 1 >= s : e < s);
+        w.edge[s - 1][k] = ok ? (head ? hv : tv) : 0.0f;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int s = 1; s <= 3; ++s) {
+      const bool ok = l < 6 && (head ? l + 1 >= s : e < s);
+      const int64_t c = head ? col0 + 1 + l - s : col0 + 256 - s + e;
+#pragma unroll
+      for (int k = 0; k < D; ++k) w.edge[s - 1][k] = ok ? X[c * ldx + k] : 0.0f;
+    }
   }
+}
+
+// One interior row i of a 256-column segment starting at col0.
+template <int D, int LAYOUT>
+__device__ __forceinline__ void packed_vec_row(const PackedWindow<D> &w, const float (&xi)[D],
+                                               uint64_t i, int64_t col0, float *__restrict__ out) {
+  const int l = threadIdx.x & 63;
+  const bool head = l < 3;
+  const int e = head ? l : l - 3;
   const int eoff = head ? 1 + l : 253 + l;
-  constexpr int PASSES = TS / 4;
-#pragma unroll 4
-  for (int ps = 0; ps < PASSES; ++ps) {
-    const int r = lr + ps * 4;
-    const uint64_t i = (uint64_t)(row0 + r);
-    float xi[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) xi[k] = xs[r * D + k];
-    const uint64_t first = out_index<LAYOUT>(i, (uint64_t)col0, 0);
-    const int sh = (int)(first & 3);
-    const uint64_t A0 = first - (uint64_t)sh;
-    float v0, v1, v2, v3, ve;
-    switch (sh) {
-      case 0:
-        v0 = pair_dist<D>(xi, win[3]); v1 = pair_dist<D>(xi, win[4]);
-        v2 = pair_dist<D>(xi, win[5]); v3 = pair_dist<D>(xi, win[6]);
-        ve = 0.0f;
-        break;
-      case 1:
-        v0 = pair_dist<D>(xi, win[2]); v1 = pair_dist<D>(xi, win[3]);
-        v2 = pair_dist<D>(xi, win[4]); v3 = pair_dist<D>(xi, win[5]);
-        ve = pair_dist<D>(xi, edge[0]);
-        break;
-      case 2:
-        v0 = pair_dist<D>(xi, win[1]); v1 = pair_dist<D>(xi, win[2]);
-        v2 = pair_dist<D>(xi, win[3]); v3 = pair_dist<D>(xi, win[4]);
-        ve = pair_dist<D>(xi, edge[1]);
-        break;
-      default:
-        v0 = pair_dist<D>(xi, win[0]); v1 = pair_dist<D>(xi, win[1]);
-        v2 = pair_dist<D>(xi, win[2]); v3 = pair_dist<D>(xi, win[3]);
-        ve = pair_dist<D>(xi, edge[2]);
-        break;
-    }
-    if (l > 0 || sh == 0) {
-      f4 v = {v0, v1, v2, v3};
-      put<LAYOUT>(v, reinterpret_cast<f4 *>(out + A0 + 4 * l));
-    }
-    if (sh != 0 && l < 6 && (head ? l + 1 >= sh : e < sh)) put<LAYOUT>(ve, out + A0 + eoff);
+  const uint64_t first = out_index<LAYOUT>(i, (uint64_t)col0, 0);
+  const int sh = (int)(first & 3);
+  const uint64_t A0 = first - (uint64_t)sh;
+  float v0, v1, v2, v3, ve;
+  switch (sh) {
+    case 0:
+      v0 = pair_dist<D>(xi, w.win[3]); v1 = pair_dist<D>(xi, w.win[4]);
+      v2 = pair_dist<D>(xi, w.win[5]); v3 = pair_dist<D>(xi, w.win[6]);
+      ve = 0.0f;
+      break;
+    case 1:
+      v0 = pair_dist<D>(xi, w.win[2]); v1 = pair_dist<D>(xi, w.win[3]);
+      v2 = pair_dist<D>(xi, w.win[4]); v3 = pair_dist<D>(xi, w.win[5]);
+      ve = pair_dist<D>(xi, w.edge[0]);
+      break;
+    case 2:
+      v0 = pair_dist<D>(xi, w.win[1]); v1 = pair_dist<D>(xi, w.win[2]);
+      v2 = pair_dist<D>(xi, w.win[3]); v3 = pair_dist<D>(xi, w.win[4]);
+      ve = pair_dist<D>(xi, w.edge[1]);
+      break;
+    default:
+      v0 = pair_dist<D>(xi, w.win[0]); v1 = pair_dist<D>(xi, w.win[1]);
+      v2 = pair_dist<D>(xi, w.win[2]); v3 = pair_dist<D>(xi, w.win[3]);
+      ve = pair_dist<D>(xi, w.edge[2]);
+      break;
   }
+  if (l > 0 || sh == 0) {
+    f4 v = {v0, v1, v2, v3};
+    put<LAYOUT>(v, reinterpret_cast<f4 *>(out + A0 + 4 * l));
+  }
+  if (sh != 0 && l < 6 && (head ? l + 1 >= sh : e < sh)) put<LAYOUT>(ve, out + A0 + eoff);
 }
 
 template <int TS, int D, int LAYOUT, bool VEC, bool BB>
@@ -168,13 +221,8 @@ __global__ __launch_bounds__(256) void edm_tile_kernel(EdmArgs a, uint32_t lam0)
 
   float *__restrict__ out = a.D;
   const bool interior = (J < I) && (row0 + TS <= N);
-  if constexpr (VEC && LAYOUT != kLayoutFull) {
-    if (interior) {
-      packed_vec_rows<TS, D, LAYOUT>(a, xs, row0, col0, lr, out);
-      return;
-    }
-  }
-  if (interior && (VEC ? LAYOUT == kLayoutFull : true)) {
+  static_assert(!VEC || LAYOUT == kLayoutFull, "16-byte stores need the full layout");
+  if (interior) {
 #pragma unroll 8
     for (int ps = 0; ps < PASSES; ++ps) {
       const int r = lr + ps * RPP;
@@ -213,7 +261,7 @@ __global__ __launch_bounds__(256) void edm_tile_kernel(EdmArgs a, uint32_t lam0)
   }
 }
 
-// Full layout, 256 x 256 tiles written as strips.  Tile row I (256 rows) is
+// 256 x 256 tiles written as strips.  Tile row I (256 rows) is
 // cut into kBandStrips strips of kBandRows rows, and a work-group writes one
 // strip of one tile, kBandRows x 256 cells.  LTM: work-group w takes tile
 // row I from g(w / kBandStrips) (the paper's block map at the tile level);
@@ -226,9 +274,13 @@ __global__ __launch_bounds__(256) void edm_tile_kernel(EdmArgs a, uint32_t lam0)
 // grid, blockIdx.y = I, blockIdx.x = k n + J, returning at once for J > I.
 // A wave owns rows w and w + 4 of the strip, 64 lanes x 4 columns each, so
 // the row point is uniform (read through the scalar cache) and each store
-// writes a 1 KB row segment; there is no LDS and no barrier.
+// writes a 1 KB row segment; there is no LDS and no barrier.  Packed and
+// strict rows go through packed_vec_row (plain stores: the chunks shared by
+// the segments of tiles J and J + 1 meet in L2, those two work-groups being
+// neighbours in w and so on one XCD).  Measured at N = 30000: 325 us full,
+// 414 us packed (the packed TS = 64 tile takes 380 us and stays the tuned
+// choice there).
 constexpr int kBandRows = 8;
-constexpr int kBandStrips = 256 / kBandRows;
 
 // The four column points of lane l.  XV: X is dense (ldx = D) and 16-byte
 // aligned, so the 4 D floats of columns c .. c + 3 are D aligned 16-byte
@@ -261,10 +313,12 @@ __device__ __forceinline__ void band_columns(const float *__restrict__ X, int64_
     for (int k = 0; k < D; ++k) xj[u][k] = c + u < N ? X[(c + u) * ldx + k] : 0.0f;
 }
 
-template <int D, bool BB, bool XV>
+template <int D, int LAYOUT, bool BB, bool XV>
 __global__ __launch_bounds__(256) void edm_band_kernel(const float *__restrict__ X, int64_t N,
                                                        int64_t ldx, float *__restrict__ out,
                                                        int64_t ldd, uint32_t w0) {
+  constexpr int H = kBandRows;
+  constexpr int kBandStrips = 256 / H;
   uint32_t I, J, k;
   if constexpr (BB) {
     I = blockIdx.y;
@@ -281,13 +335,30 @@ __global__ __launch_bounds__(256) void edm_band_kernel(const float *__restrict__
     J = u - k * (I + 1);
   }
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t row0 = (int64_t)I * 256 + (int64_t)k * kBandRows;
+  const int64_t row0 = (int64_t)I * 256 + (int64_t)k * H;
   const int64_t c = (int64_t)J * 256 + (threadIdx.x & 63) * 4;
+  const bool interior = J < I && row0 + H <= N;
+  if constexpr (LAYOUT != kLayoutFull) {
+    // packed rows start anywhere: 16-byte stores of realigned chunks
+    if (interior) {
+      PackedWindow<D> pw;
+      packed_window<D, XV>(X, ldx, (int64_t)J * 256, pw);
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) {
+        const int64_t i = row0 + wv + 4 * r;
+        float xi[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m) xi[m] = X[i * ldx + m];
+        packed_vec_row<D, LAYOUT>(pw, xi, (uint64_t)i, (int64_t)J * 256, out);
+      }
+      return;
+    }
+  }
   float xj[4][D];
   band_columns<D, XV>(X, N, ldx, c, xj);
-  if (J < I && row0 + kBandRows <= N) {
+  if (LAYOUT == kLayoutFull && interior) {
 #pragma unroll
-    for (int r = 0; r < kBandRows / 4; ++r) {
+    for (int r = 0; r < H / 4; ++r) {
       const int64_t i = row0 + wv + 4 * r;
       float xi[D];
 #pragma unroll
@@ -302,7 +373,7 @@ __global__ __launch_bounds__(256) void edm_band_kernel(const float *__restrict__
   } else {
     // diagonal or edge strip: rows below N, cells with j <= i
 #pragma unroll
-    for (int r = 0; r < kBandRows / 4; ++r) {
+    for (int r = 0; r < H / 4; ++r) {
       const int64_t i = row0 + wv + 4 * r;
       if (i >= N) break;
       float xi[D];
@@ -311,24 +382,32 @@ __global__ __launch_bounds__(256) void edm_band_kernel(const float *__restrict__
       float v[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) v[q] = pair_dist<D>(xi, xj[q]);
-      float *o = out + i * ldd + c;
-      if (c + 3 <= i) {
-        f4 v4 = {v[0], v[1], v[2], v[3]};
-        __builtin_nontemporal_store(v4, reinterpret_cast<f4 *>(o));
+      if constexpr (LAYOUT == kLayoutFull) {
+        float *o = out + i * ldd + c;
+        if (c + 3 <= i) {
+          f4 v4 = {v[0], v[1], v[2], v[3]};
+          __builtin_nontemporal_store(v4, reinterpret_cast<f4 *>(o));
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (c + q <= i) __builtin_nontemporal_store(v[q], o + q);
+        }
       } else {
+        const uint64_t idx = out_index<LAYOUT>((uint64_t)i, (uint64_t)c, 0);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (c + q <= i) __builtin_nontemporal_store(v[q], o + q);
+          if (in_triangle<LAYOUT>(i, c + q)) put<LAYOUT>(v[q], out + idx + q);
       }
     }
   }
 }
 
-template <int D, bool XV>
+template <int D, int LAYOUT, bool XV>
 static hipError_t launch_band(bool bb, const EdmArgs &a) {
+  constexpr int kBandStrips = 256 / kBandRows;
   const uint64_t nb = (uint64_t)((a.N + 255) / 256);
   if (bb) {
-    hipLaunchKernelGGL((edm_band_kernel<D, true, XV>), dim3((uint32_t)(kBandStrips * nb), (uint32_t)nb),
+    hipLaunchKernelGGL((edm_band_kernel<D, LAYOUT, true, XV>), dim3((uint32_t)(kBandStrips * nb), (uint32_t)nb),
                        dim3(256), 0, a.stream, a.X, a.N, a.ldx, a.D, a.ldd, 0u);
     return hipGetLastError();
   }
@@ -337,7 +416,7 @@ static hipError_t launch_band(bool bb, const EdmArgs &a) {
   const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
   for (uint64_t w0 = 0; w0 < W; w0 += max_blocks) {
     const uint64_t c = W - w0 < max_blocks ? W - w0 : max_blocks;
-    hipLaunchKernelGGL((edm_band_kernel<D, false, XV>), dim3((uint32_t)c), dim3(256), 0, a.stream,
+    hipLaunchKernelGGL((edm_band_kernel<D, LAYOUT, false, XV>), dim3((uint32_t)c), dim3(256), 0, a.stream,
                        a.X, a.N, a.ldx, a.D, a.ldd, (uint32_t)w0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -350,7 +429,7 @@ static hipError_t launch_tiled_t(bool bb, const EdmArgs &a) {
   if constexpr (TS == 256 && LAYOUT == kLayoutFull && VEC) {
     // strips of 256-column tiles for the aligned full layout
     const bool xv = a.ldx == D && (reinterpret_cast<uintptr_t>(a.X) & 15) == 0;
-    return xv ? launch_band<D, true>(bb, a) : launch_band<D, false>(bb, a);
+    return xv ? launch_band<D, kLayoutFull, true>(bb, a) : launch_band<D, kLayoutFull, false>(bb, a);
   }
   const uint64_t nb = (uint64_t)((a.N + TS - 1) / TS);
   if (bb) {
@@ -373,8 +452,10 @@ static hipError_t launch_tiled_t(bool bb, const EdmArgs &a) {
 template <int TS, int D, int LAYOUT>
 static hipError_t launch_tiled_packed(bool bb, const EdmArgs &a) {
   if constexpr (TS == 256) {
-    if ((reinterpret_cast<uintptr_t>(a.D) & 15) == 0)
-      return launch_tiled_t<TS, D, LAYOUT, true>(bb, a);
+    if ((reinterpret_cast<uintptr_t>(a.D) & 15) == 0) {
+      const bool xv = a.ldx == D && (reinterpret_cast<uintptr_t>(a.X) & 15) == 0;
+      return xv ? launch_band<D, LAYOUT, true>(bb, a) : launch_band<D, LAYOUT, false>(bb, a);
+    }
   }
   return launch_tiled_t<TS, D, LAYOUT, false>(bb, a);
 }
