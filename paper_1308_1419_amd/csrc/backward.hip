@@ -417,17 +417,25 @@ __global__ __launch_bounds__(256) void edm_bwd_tile256(BwdArgs a, uint32_t lam0)
 
 // Deterministic second pass: point p in block B = p / TS collects nb + 1
 // partials: entry t <= B is the row partial of tile (B, t), entry t > B the
-// column partial of tile (B + t - B - 1, B).  Eight accumulators take every
-// eighth entry (eight loads in flight per thread) and are added in a fixed
-// tree, so the result does not depend on timing.
+// column partial of tile (B + t - B - 1, B).  The work-group holds G
+// groups of TS d threads (G = 1024 / (TS d), at most 4); group g takes the
+// entries t = g mod G with eight accumulators (every eighth of its entries,
+// eight loads in flight per thread), and the G group sums are added in
+// group order, so the result does not depend on timing.
+template <int E>
+constexpr int bwd_reduce_groups() {
+  return 1024 / E >= 4 ? 4 : (1024 / E >= 2 ? 2 : 1);
+}
+
 template <int TS, int D>
-__global__ __launch_bounds__(TS * D) void edm_bwd_reduce(const float *__restrict__ ws,
-                                                         float *__restrict__ dX, int64_t N,
-                                                         uint32_t nb) {
+__global__ __launch_bounds__(TS * D * bwd_reduce_groups<TS * D>()) void edm_bwd_reduce(
+    const float *__restrict__ ws, float *__restrict__ dX, int64_t N, uint32_t nb) {
+  constexpr int G = bwd_reduce_groups<TS * D>();
+  constexpr int E = TS * D;
   const uint32_t B = blockIdx.x;
-  const int e = threadIdx.x;
+  const int e = threadIdx.x % E;
+  const int g = threadIdx.x / E;
   const int64_t p = (int64_t)B * TS + e / D;
-  if (p >= N) return;
   constexpr int STRIDE = 2 * TS * D;
   const uint64_t tb = tri64(B);
   auto entry = [&](uint32_t t) -> float {
@@ -436,17 +444,32 @@ __global__ __launch_bounds__(TS * D) void edm_bwd_reduce(const float *__restrict
   };
   const uint32_t cnt = nb + 1;
   float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  uint32_t t = 0;
-  for (; t + 8 <= cnt; t += 8) {
-    float v[8];
+  if (p < N) {
+    uint32_t t = g;
+    for (; t + 7 * G < cnt; t += 8 * G) {
+      float v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = entry(t + u);
+      for (int u = 0; u < 8; ++u) v[u] = entry(t + u * G);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] += v[u];
+      for (int u = 0; u < 8; ++u) acc[u] += v[u];
+    }
+    for (; t < cnt; t += G) acc[0] += entry(t);
   }
-  for (; t < cnt; ++t) acc[0] += entry(t);
-  dX[(uint64_t)B * TS * D + e] =
+  const float part =
       ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  if constexpr (G == 1) {
+    if (p < N) dX[(uint64_t)B * TS * D + e] = part;
+  } else {
+    __shared__ float red[G][E];
+    red[g][e] = part;
+    __syncthreads();
+    if (g == 0 && p < N) {
+      float sum = red[0][e];
+#pragma unroll
+      for (int q = 1; q < G; ++q) sum += red[q][e];
+      dX[(uint64_t)B * TS * D + e] = sum;
+    }
+  }
 }
 
 template <int TS, int D, int LAYOUT, bool DET>
@@ -470,8 +493,9 @@ static hipError_t launch_bwd_t(const BwdArgs &a) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (DET) {
-    hipLaunchKernelGGL((edm_bwd_reduce<TS, D>), dim3((uint32_t)nb), dim3(TS * D), 0, a.stream,
-                       a.ws, a.dX, a.N, (uint32_t)nb);
+    hipLaunchKernelGGL((edm_bwd_reduce<TS, D>), dim3((uint32_t)nb),
+                       dim3(TS * D * bwd_reduce_groups<TS * D>()), 0, a.stream, a.ws, a.dX, a.N,
+                       (uint32_t)nb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -500,14 +524,23 @@ static hipError_t launch_bwd_ts(const BwdArgs &a) {
 }
 
 // Deterministic total of the per-tile losses: one work-group, thread t
-// adds entries t, t + 1024, ... in order, then a fixed tree.
+// takes entries t, t + 1024, ... into eight accumulators (entry t + 1024 m
+// into accumulator m mod 8), then a fixed tree.
 __global__ __launch_bounds__(1024) void stress_loss_reduce(const float *__restrict__ part,
                                                            uint64_t count, float *__restrict__ loss) {
   __shared__ float buf[1024];
   const int t = threadIdx.x;
-  float acc = 0.0f;
-  for (uint64_t e = t; e < count; e += 1024) acc += part[e];
-  buf[t] = acc;
+  float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  uint64_t e = t;
+  for (; e + 7 * 1024 < count; e += 8 * 1024) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[e + 1024 * u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += v[u];
+  }
+  for (; e < count; e += 1024) acc[0] += part[e];
+  buf[t] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
   for (int off = 512; off > 0; off >>= 1) {
     if (t < off) buf[t] += buf[t + off];
@@ -533,8 +566,9 @@ static hipError_t launch_stress_t(const BwdArgs &a) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (DET) {
-    hipLaunchKernelGGL((edm_bwd_reduce<TS, D>), dim3((uint32_t)nb), dim3(TS * D), 0, a.stream,
-                       a.ws, a.dX, a.N, (uint32_t)nb);
+    hipLaunchKernelGGL((edm_bwd_reduce<TS, D>), dim3((uint32_t)nb),
+                       dim3(TS * D * bwd_reduce_groups<TS * D>()), 0, a.stream, a.ws, a.dX, a.N,
+                       (uint32_t)nb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(stress_loss_reduce, dim3(1), dim3(1024), 0, a.stream, a.ws_loss, T, a.loss);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -114,7 +114,12 @@ __device__ __forceinline__ int row_shift(int rr) {
   return ((m * (m + 1)) >> 1) & 3;
 }
 
-template <bool SPLIT>
+
+// KPC: the padded feature count as a compile-time constant (16, 32, 64 or
+// 128), which unrolls the MFMA loop so that the loads of every feature step
+// are issued before the first product waits (measured: split form 9.5 ->
+// 8.7 ms at N = 100000, d = 64); 0 for any other count.
+template <bool SPLIT, int KPC>
 __global__ __launch_bounds__(256, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs a, uint32_t lam0,
                                                                       uint32_t nblk) {
   // Each XCD takes one contiguous range of lambda: neighbouring tiles share
@@ -137,7 +142,7 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
   // on a diagonal tile, column blocks right of this wave's rows are above
   // the diagonal
   const int nbj = diag ? w + 1 : 4;
-  const int KP = a.KP;
+  const int KP = KPC ? KPC : a.KP;
   const uint16_t *__restrict__ Xb = a.Xb;
 
   float nr[16];
@@ -156,6 +161,7 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
   // [8 (l / 32), 8 (l / 32) + 8) of each 16-feature step; B uses the same
   // assignment for its points, so the product is x_i . x_j.
   const uint16_t *__restrict__ Xl = a.Xlo;
+#pragma unroll
   for (int k = 0; k < KP; k += 16) {
     const int64_t ao = (rw + lr) * KP + k + lk;
     const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Xb + ao);
@@ -275,6 +281,27 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
   }
 }
 
+template <bool SPLIT>
+static void launch_gram_tiles(int KP, dim3 grid, hipStream_t stream, const GramArgs &a, uint32_t l0) {
+  const dim3 block(256);
+  switch (KP) {
+    case 16:
+      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 16>), grid, block, 0, stream, a, l0, grid.x);
+      break;
+    case 32:
+      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 32>), grid, block, 0, stream, a, l0, grid.x);
+      break;
+    case 64:
+      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 64>), grid, block, 0, stream, a, l0, grid.x);
+      break;
+    case 128:
+      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 128>), grid, block, 0, stream, a, l0, grid.x);
+      break;
+    default:
+      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 0>), grid, block, 0, stream, a, l0, grid.x);
+  }
+}
+
 size_t gram_workspace_bytes(int64_t N, int d, bool split) {
   const int64_t Npad = (N + kGramTile - 1) / kGramTile * kGramTile;
   const int64_t KP = (d + 15) / 16 * 16;
@@ -302,11 +329,9 @@ hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, 
   for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
     const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
     if (split)
-      hipLaunchKernelGGL(gram_tile_kernel<true>, dim3((uint32_t)c), dim3(256), 0, stream, a,
-                         (uint32_t)l0, (uint32_t)c);
+      launch_gram_tiles<true>(KP, dim3((uint32_t)c), stream, a, (uint32_t)l0);
     else
-      hipLaunchKernelGGL(gram_tile_kernel<false>, dim3((uint32_t)c), dim3(256), 0, stream, a,
-                         (uint32_t)l0, (uint32_t)c);
+      launch_gram_tiles<false>(KP, dim3((uint32_t)c), stream, a, (uint32_t)l0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
