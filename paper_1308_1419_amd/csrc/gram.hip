@@ -161,8 +161,7 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
   // [8 (l / 32), 8 (l / 32) + 8) of each 16-feature step; B uses the same
   // assignment for its points, so the product is x_i . x_j.
   const uint16_t *__restrict__ Xl = a.Xlo;
-#pragma unroll
-  for (int k = 0; k < KP; k += 16) {
+  auto kstep = [&](int k) {
     const int64_t ao = (rw + lr) * KP + k + lk;
     const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Xb + ao);
     bf16x8 al;
@@ -180,6 +179,12 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
         acc[bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[bj], 0, 0, 0);
       }
     }
+  };
+  if constexpr (KPC != 0) {
+#pragma unroll
+    for (int k = 0; k < KPC; k += 16) kstep(k);
+  } else {
+    for (int k = 0; k < KP; k += 16) kstep(k);
   }
 
   // stage row rr holds column c at position c + sh(rr), where sh(rr) is the

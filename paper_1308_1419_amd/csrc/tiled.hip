@@ -20,11 +20,10 @@
 // the diagonal (Sec. III-B), with the same tile body, which makes the two
 // directly comparable.
 //
-// TS = 256 with a 16-byte aligned output: edm_band_kernel below, which
-// writes each tile as 8-row strips (one strip per work-group, no LDS, row
-// points through the scalar cache; packed rows are realigned to 16-byte
-// chunks).  TS = 64 / 128, and TS = 256 with an unaligned output:
-// edm_tile_kernel.
+// TS = 256: edm_band_kernel below, which writes each tile as 8-row strips
+// (one strip per work-group, no LDS, row points through the scalar cache);
+// the full layout needs a 16-byte aligned output (else edm_tile_kernel).
+// TS = 64 / 128: edm_tile_kernel.
 #include "device.h"
 #include "kernels.h"
 
@@ -44,140 +43,6 @@ __device__ __forceinline__ void put(T v, T *p) {
     __builtin_nontemporal_store(v, p);
   else
     *p = v;
-}
-
-// Interior rows of a 256-column segment in the packed layout with 16-byte
-// stores (one row per wave and call).  Packed row i starts at R(i) = i(i+1)/2 (or
-// i(i-1)/2 without the diagonal), so the tile's row segment
-// [col0, col0 + 256) begins s = (R(i) + col0) mod 4 positions past a
-// 16-byte boundary.  Lane l stores the aligned chunk
-// holding columns col0 - s + 4l .. col0 - s + 4l + 3; for lanes 1..63 those
-// all lie in the segment, so each of them needs the points of columns
-// col0 + 4l - 3 .. col0 + 4l + 3 (kept in registers) and picks four of them
-// by s, which is uniform across the wave.  The 4 - s head cells and the s
-// tail cells (col0 + 256 - s .. col0 + 255) go out in one 4-byte store
-// instruction from lanes 0..5: lanes 0..2 own chunk positions 1..3 of the
-// first chunk, lanes 3..5 positions 0..2 of the chunk after the last full
-// one, and each keeps the point it needs for every s.  The neighbouring
-// tiles write the rest of the two shared chunks.
-template <int D>
-struct PackedWindow {
-  float win[7][D];   // columns col0 + 4l - 3 .. col0 + 4l + 3
-  float edge[3][D];  // the edge lane's point for s = 1, 2, 3
-};
-
-__device__ __forceinline__ float lane_value(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-
-// XV: X is dense (ldx = D) and 16-byte aligned; the window of lane l is
-// then read as 2 D aligned 16-byte chunks (columns col0 + 4l - 4 ..
-// col0 + 4l + 3) and the edge points are taken from the windows of lanes 0
-// and 63 instead of from memory (every lane of the wave must be active).
-template <int D, bool XV = false>
-__device__ __forceinline__ void packed_window(const float *__restrict__ X, int64_t ldx, int64_t col0,
-                                              PackedWindow<D> &w) {
-  const int l = threadIdx.x & 63;
-  const int64_t c0 = col0 + 4 * l - 4;
-  if (XV && c0 >= 0) {
-    const f4 *q = reinterpret_cast<const f4 *>(X + c0 * D);
-    float v[8 * D];
-#pragma unroll
-    for (int m = 0; m < 2 * D; ++m) {
-      const f4 t = q[m];
-      v[4 * m] = t.x;
-      v[4 * m + 1] = t.y;
-      v[4 * m + 2] = t.z;
-      v[4 * m + 3] = t.w;
-    }
-#pragma unroll
-    for (int o = 0; o < 7; ++o)
-#pragma unroll
-      for (int k = 0; k < D; ++k) w.win[o][k] = v[(o + 1) * D + k];
-  } else {
-#pragma unroll
-    for (int o = 0; o < 7; ++o) {
-      const int64_t c = c0 + 1 + o;
-#pragma unroll
-      for (int k = 0; k < D; ++k) w.win[o][k] = c >= 0 ? X[c * ldx + k] : 0.0f;
-    }
-  }
-  // edge lane e = l (head, l < 3) or l - 3 (tail, 3 <= l < 6); for shift s
-  // it owns column col0 + 1 + l - s (head, kept when l + 1 >= s) or
-  // col0 + 256 - s + e (tail, kept when e < s), at packed offset
-  // A0 + 1 + l or A0 + 253 + l
-  const bool head = l < 3;
-  const int e = head ? l : l - 3;
-  if constexpr (XV) {
-    // column col0 + 1 + l - s is lane 0's win[4 + l - s] (index 1..5);
-    // column col0 + 256 - s + e is lane 63's win[7 - s + e] (4..6 when kept)
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      float h[6], t[7];
-#pragma unroll
-      for (int o = 1; o <= 5; ++o) h[o] = lane_value(w.win[o][k], 0);
-#pragma unroll
-      for (int o = 4; o <= 6; ++o) t[o] = lane_value(w.win[o][k], 63);
-#pragma unroll
-      for (int s = 1; s <= 3; ++s) {
-        const int oh = 4 + l - s;
-        const int ot = 7 - s + e;
-        const float hv = oh <= 1 ? h[1] : oh == 2 ? h[2] : oh == 3 ? h[3] : oh == 4 ? h[4] : h[5];
-        const float tv = ot <= 4 ? t[4] : ot == 5 ? t[5] : t[6];
-        const bool ok = l < 6 && (head ? l + 1 >= s : e < s);
-        w.edge[s - 1][k] = ok ? (head ? hv : tv) : 0.0f;
-      }
-    }
-  } else {
-#pragma unroll
-    for (int s = 1; s <= 3; ++s) {
-      const bool ok = l < 6 && (head ? l + 1 >= s : e < s);
-      const int64_t c = head ? col0 + 1 + l - s : col0 + 256 - s + e;
-#pragma unroll
-      for (int k = 0; k < D; ++k) w.edge[s - 1][k] = ok ? X[c * ldx + k] : 0.0f;
-    }
-  }
-}
-
-// One interior row i of a 256-column segment starting at col0.
-template <int D, int LAYOUT>
-__device__ __forceinline__ void packed_vec_row(const PackedWindow<D> &w, const float (&xi)[D],
-                                               uint64_t i, int64_t col0, float *__restrict__ out) {
-  const int l = threadIdx.x & 63;
-  const bool head = l < 3;
-  const int e = head ? l : l - 3;
-  const int eoff = head ? 1 + l : 253 + l;
-  const uint64_t first = out_index<LAYOUT>(i, (uint64_t)col0, 0);
-  const int sh = (int)(first & 3);
-  const uint64_t A0 = first - (uint64_t)sh;
-  float v0, v1, v2, v3, ve;
-  switch (sh) {
-    case 0:
-      v0 = pair_dist<D>(xi, w.win[3]); v1 = pair_dist<D>(xi, w.win[4]);
-      v2 = pair_dist<D>(xi, w.win[5]); v3 = pair_dist<D>(xi, w.win[6]);
-      ve = 0.0f;
-      break;
-    case 1:
-      v0 = pair_dist<D>(xi, w.win[2]); v1 = pair_dist<D>(xi, w.win[3]);
-      v2 = pair_dist<D>(xi, w.win[4]); v3 = pair_dist<D>(xi, w.win[5]);
-      ve = pair_dist<D>(xi, w.edge[0]);
-      break;
-    case 2:
-      v0 = pair_dist<D>(xi, w.win[1]); v1 = pair_dist<D>(xi, w.win[2]);
-      v2 = pair_dist<D>(xi, w.win[3]); v3 = pair_dist<D>(xi, w.win[4]);
-      ve = pair_dist<D>(xi, w.edge[1]);
-      break;
-    default:
-      v0 = pair_dist<D>(xi, w.win[0]); v1 = pair_dist<D>(xi, w.win[1]);
-      v2 = pair_dist<D>(xi, w.win[2]); v3 = pair_dist<D>(xi, w.win[3]);
-      ve = pair_dist<D>(xi, w.edge[2]);
-      break;
-  }
-  if (l > 0 || sh == 0) {
-    f4 v = {v0, v1, v2, v3};
-    put<LAYOUT>(v, reinterpret_cast<f4 *>(out + A0 + 4 * l));
-  }
-  if (sh != 0 && l < 6 && (head ? l + 1 >= sh : e < sh)) put<LAYOUT>(ve, out + A0 + eoff);
 }
 
 template <int TS, int D, int LAYOUT, bool VEC, bool BB>
@@ -272,14 +137,16 @@ __global__ __launch_bounds__(256) void edm_tile_kernel(EdmArgs a, uint32_t lam0)
 // write stream stays within a compact window of addresses; measured 15 %
 // faster than whole-tile work-groups at N = 30000).  BB: a kBandStrips n x n
 // grid, blockIdx.y = I, blockIdx.x = k n + J, returning at once for J > I.
-// A wave owns rows w and w + 4 of the strip, 64 lanes x 4 columns each, so
-// the row point is uniform (read through the scalar cache) and each store
-// writes a 1 KB row segment; there is no LDS and no barrier.  Packed and
-// strict rows go through packed_vec_row (plain stores: the chunks shared by
-// the segments of tiles J and J + 1 meet in L2, those two work-groups being
-// neighbours in w and so on one XCD).  Measured at N = 30000: 325 us full,
-// 414 us packed (the packed TS = 64 tile takes 380 us and stays the tuned
-// choice there).
+// A wave owns rows w and w + 4 of the strip, so the row point is uniform
+// (read through the scalar cache); there is no LDS and no barrier.  Full
+// layout: a lane owns four consecutive columns and each non-temporal
+// 16-byte store writes a 1 KB row segment.  Packed layouts (rows start at
+// any offset): a lane owns columns l, l + 64, l + 128, l + 192 and each
+// plain 4-byte store instruction writes 256 contiguous bytes; the lines
+// shared by the segments of tiles J and J + 1 meet in L2, those two
+// work-groups being neighbours in w and so on one XCD.  Measured at
+// N = 30000: 323 us full (16-byte and 4-byte stores alike), 292 us packed
+// (16-byte stores of realigned chunks: 414 us).
 constexpr int kBandRows = 8;
 
 // The four column points of lane l.  XV: X is dense (ldx = D) and 16-byte
@@ -339,17 +206,24 @@ __global__ __launch_bounds__(256) void edm_band_kernel(const float *__restrict__
   const int64_t c = (int64_t)J * 256 + (threadIdx.x & 63) * 4;
   const bool interior = J < I && row0 + H <= N;
   if constexpr (LAYOUT != kLayoutFull) {
-    // packed rows start anywhere: 16-byte stores of realigned chunks
+    // packed rows start anywhere: lane l owns columns col0 + l + 64 q and a
+    // store instruction writes 256 contiguous bytes (plain stores)
     if (interior) {
-      PackedWindow<D> pw;
-      packed_window<D, XV>(X, ldx, (int64_t)J * 256, pw);
+      const int64_t cb = (int64_t)J * 256 + (threadIdx.x & 63);
+      float xq[4][D];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int m = 0; m < D; ++m) xq[q][m] = X[(cb + 64 * q) * ldx + m];
 #pragma unroll
       for (int r = 0; r < H / 4; ++r) {
         const int64_t i = row0 + wv + 4 * r;
         float xi[D];
 #pragma unroll
         for (int m = 0; m < D; ++m) xi[m] = X[i * ldx + m];
-        packed_vec_row<D, LAYOUT>(pw, xi, (uint64_t)i, (int64_t)J * 256, out);
+        float *o = out + out_index<LAYOUT>((uint64_t)i, (uint64_t)cb, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) put<LAYOUT>(pair_dist<D>(xi, xq[q]), o + 64 * q);
       }
       return;
     }
@@ -452,10 +326,8 @@ static hipError_t launch_tiled_t(bool bb, const EdmArgs &a) {
 template <int TS, int D, int LAYOUT>
 static hipError_t launch_tiled_packed(bool bb, const EdmArgs &a) {
   if constexpr (TS == 256) {
-    if ((reinterpret_cast<uintptr_t>(a.D) & 15) == 0) {
-      const bool xv = a.ldx == D && (reinterpret_cast<uintptr_t>(a.X) & 15) == 0;
-      return xv ? launch_band<D, LAYOUT, true>(bb, a) : launch_band<D, LAYOUT, false>(bb, a);
-    }
+    const bool xv = a.ldx == D && (reinterpret_cast<uintptr_t>(a.X) & 15) == 0;
+    return xv ? launch_band<D, LAYOUT, true>(bb, a) : launch_band<D, LAYOUT, false>(bb, a);
   }
   return launch_tiled_t<TS, D, LAYOUT, false>(bb, a);
 }

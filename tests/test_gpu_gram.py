@@ -37,7 +37,7 @@ def _check_rows(X, rows, got_rows, split=False):
     X64 = X.astype(np.float64)
     norms = np.linalg.norm(X64, axis=1)
     ref_rows = native.edm_rows(X, rows)
-    stats = {"max_abs": 0.0, "max_rel": 0.0, "n": 0}
+    stats = {"max_abs": 0.0, "max_rel": 0.0, "n": 0, "sq_rel": 0.0, "fp32_rule": 0}
     for i, got, ref in zip(rows, got_rows, ref_rows):
         got = np.asarray(got, dtype=np.float64)
         assert got[i] == 0.0, f"diagonal ({i},{i}) = {got[i]}"
@@ -49,8 +49,12 @@ def _check_rows(X, rows, got_rows, split=False):
         nz = ref > 0
         stats["max_abs"] = max(stats["max_abs"], float(err.max()))
         if nz.any():
-            stats["max_rel"] = max(stats["max_rel"], float((err[nz] / ref[nz]).max()))
+            rel = err[nz] / ref[nz]
+            stats["max_rel"] = max(stats["max_rel"], float(rel.max()))
+            stats["sq_rel"] += float(np.dot(rel, rel))
+        stats["fp32_rule"] += int(np.sum(err <= REL * ref))
         stats["n"] += len(ref)
+    stats["rms_rel"] = (stats["sq_rel"] / max(stats["n"], 1)) ** 0.5
     return stats
 
 
@@ -123,7 +127,8 @@ def test_gram_workload_full_size(prec):
         got_rows.append(D[k: k + i + 1].cpu().numpy())
     stats = _check_rows(X, rows, got_rows, split=prec == "bf16x3_gram")
     print(f"{prec} N=100000 d=64: {stats['n']} pairs checked, max abs err {stats['max_abs']:.3e}, "
-          f"max rel err {stats['max_rel']:.3e}", flush=True)
+          f"max rel err {stats['max_rel']:.3e}, rms rel err {stats['rms_rel']:.3e}, "
+          f"{stats['fp32_rule']} pairs within 1e-6 relative", flush=True)
     # every planted pair meets the FP32 rule
     idx = torch.as_tensor([oedm.tri(int(max(c, s))) + int(min(c, s)) for c, s in pairs],
                           device="cuda")
