@@ -62,10 +62,12 @@ void tuned_store(const TuneKey &k, int v) {
 }
 
 // Runs launch(c) for every candidate c: one warm-up each, then `reps`
-// rounds in which every candidate is timed once, median of its times.  The
-// rounds interleave the candidates because the device's speed drifts over a
-// burst of back-to-back launches (clocks settle), which would otherwise
-// favour whichever candidate is timed first.  Returns the fastest candidate
+// rounds in which every candidate is timed over `burst` back-to-back
+// launches, median of its per-launch times.  The rounds interleave the
+// candidates because the device's speed drifts over a burst of launches
+// (clocks settle), which would otherwise favour whichever candidate is
+// timed first; the bursts keep the launch latency and the first launch
+// after an idle gap out of the comparison.  Returns the fastest candidate
 // (0 on error, with *status set).
 template <class F>
 int autotune(const std::vector<int> &cands, hipStream_t s, F launch, int *status) {
@@ -77,6 +79,7 @@ int autotune(const std::vector<int> &cands, hipStream_t s, F launch, int *status
     return 0;
   }
   const int reps = 5;
+  const int burst = 3;
   std::vector<std::vector<float>> ms(cands.size());
   for (size_t k = 0; k < cands.size() && *status == TDMAP_OK; ++k) {
     const hipError_t e = launch(cands[k]);
@@ -85,7 +88,7 @@ int autotune(const std::vector<int> &cands, hipStream_t s, F launch, int *status
   for (int r = 0; r < reps && *status == TDMAP_OK; ++r) {
     for (size_t k = 0; k < cands.size(); ++k) {
       hipError_t e = hipEventRecord(ev[0], s);
-      if (e == hipSuccess) e = launch(cands[k]);
+      for (int b = 0; b < burst && e == hipSuccess; ++b) e = launch(cands[k]);
       if (e == hipSuccess) e = hipEventRecord(ev[1], s);
       if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
       if (e != hipSuccess) {
@@ -94,7 +97,7 @@ int autotune(const std::vector<int> &cands, hipStream_t s, F launch, int *status
       }
       float t = 0.0f;
       (void)hipEventElapsedTime(&t, ev[0], ev[1]);
-      ms[k].push_back(t);
+      ms[k].push_back(t / burst);
     }
   }
   int best = 0;
