@@ -280,10 +280,14 @@ def row_batched(torch, tdmap, synth):
                      dtype=torch.uint8, device="cuda")
     fn = lambda: tdmap.edm_batched(Xd, po, oo, rho=0, out=D, workspace=ws)
     t = _med_ms(fn, 10)
+    per_rho = {}
+    for rho in (1, 64, 128):
+        per_rho[f"rho{rho}_us"] = _med_ms(
+            lambda rho=rho: tdmap.edm_batched(Xd, po, oo, rho=rho, out=D, workspace=ws), 5) * 1e3
     del D
     return {"sets": 4096, "pairs": total, "us": t * 1e3, "pairs_per_s": total / (t * 1e-3),
             "hbm_frac": 4 * total / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "rho": tdmap.tdmap_tuned_rho(tdmap.OP_BATCHED, 0, 0, 3, 4096)}
+            "rho": tdmap.tdmap_tuned_rho(tdmap.OP_BATCHED, 0, 0, 3, 4096), **per_rho}
 
 
 def first_map_failure(torch, tdmap, variant, chunk=1 << 27):

@@ -55,10 +55,10 @@ def _run(sizes, d, rho, seed, guard=256):
 
 
 @pytest.mark.parametrize("rho", [1, 64, 128, 0])
-@pytest.mark.parametrize("d", [1, 3, 4])
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
 def test_batched_ragged_sets(rho, d):
     _require_gpu()
-    sizes = [5, 0, 1, 2, 63, 64, 65, 0, 200, 129, 300, 7]
+    sizes = [5, 0, 1, 2, 63, 64, 65, 0, 200, 129, 300, 7, 255, 256, 257, 520, 0, 1030]
     X, po, oo, buf = _run(sizes, d, rho, seed=d * 10 + rho)
     got = buf.cpu().numpy()
     ref = oedm.edm64_batched(X, po)
@@ -112,12 +112,16 @@ def test_batched_workload_full_size():
     pod, ood = torch.from_numpy(po).cuda(), torch.from_numpy(oo).cuda()
     tdmap.edm_batched(Xd, pod, ood, rho=0, out=buf[:total])
     torch.cuda.synchronize()
-    # the two persistent walks (linear sweep, tiles) write identical bits
+    # every persistent walk (linear sweep, 64- and 128-cell tiles) writes
+    # the same bits
     other = torch.empty(total, dtype=torch.float32, device="cuda")
     chosen = tdmap.tdmap_tuned_rho(tdmap.OP_BATCHED, 0, 0, 3, 4096)
-    tdmap.edm_batched(Xd, pod, ood, rho=64 if chosen == 1 else 1, out=other)
-    torch.cuda.synchronize()
-    assert torch.equal(other.view(torch.int32), buf[:total].view(torch.int32))
+    for rho in (1, 64, 128):
+        if rho == chosen:
+            continue
+        tdmap.edm_batched(Xd, pod, ood, rho=rho, out=other)
+        torch.cuda.synchronize()
+        assert torch.equal(other.view(torch.int32), buf[:total].view(torch.int32)), rho
     del other
     bits = buf.view(torch.int32)
     assert not bool(torch.any(bits[:total] == SENTINEL)), "a cell was not written"
