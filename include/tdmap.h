@@ -123,12 +123,22 @@ int tdmap_map_blocks_nodiag(uint64_t lambda0, uint64_t count, uint32_t *ij, void
  *                          thread;
  *              8, 16, 32 : rho x rho threads per block, one cell per thread,
  *                          as the paper launches every strategy;
- *              64, 128, 256 : (LTM, BB) rho x rho cell tiles per 256-thread
+ *              64, 128  : (LTM, BB) rho x rho cell tiles per 256-thread
  *                          work-group (full layout: four consecutive cells
  *                          per thread and row; packed layouts: one cell per
- *                          thread and row, except rho = 256 with D 16-byte
- *                          aligned); LTM tiles are taken by g(lambda) with
- *                          every XCD owning one contiguous range of lambda;
+ *                          thread and row); LTM tiles are taken by g(lambda)
+ *                          with every XCD owning one contiguous range of
+ *                          lambda;
+ *              256       : (LTM, BB) 256 x 256 tiles, each written by 32
+ *                          work-groups of 8 rows (strips).  LTM: the tile
+ *                          row comes from g(lambda) on the strip index
+ *                          divided by 32, and the strips of a tile row are
+ *                          taken strip by strip across the row.  Full
+ *                          layout: four consecutive cells per thread and
+ *                          row, 16-byte stores (D 16-byte aligned and ldd a
+ *                          multiple of 4, else the 256-cell tile of the
+ *                          rho = 64 / 128 form); packed layouts: four cells
+ *                          64 apart per thread and row;
  *              0         : (LTM, BB) chosen by the autotuner among the
  *                          tiles (and, for LTM with a packed layout and an
  *                          aligned D, the sweep rho = 1), timed on the
