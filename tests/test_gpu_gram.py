@@ -59,8 +59,8 @@ def _check_rows(X, rows, got_rows, split=False):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("N", [1, 2, 63, 64, 65, 127, 128, 129, 300, 1000])
-@pytest.mark.parametrize("d", [1, 3, 16, 64, 100])
+@pytest.mark.parametrize("N", [1, 2, 15, 16, 17, 63, 64, 65, 127, 128, 129, 255, 256, 257, 300, 1000])
+@pytest.mark.parametrize("d", [1, 3, 16, 33, 64, 100])
 def test_gram_small(N, d, prec):
     _require_gpu()
     X, pairs = synth.gaussian_with_near_duplicates(N, d, seed=500 + N + d, frac=0.05)
