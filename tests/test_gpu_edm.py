@@ -238,6 +238,45 @@ def test_edm_tiled_packed_and_unaligned(strategy, rho, d):
     _check_full(F, X, ld=N + 1)
 
 
+@pytest.mark.parametrize("strategy", ["ltm", "bb"])
+@pytest.mark.parametrize("pitched", [False, True])
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+@pytest.mark.parametrize("N", [1, 7, 8, 9, 255, 256, 257, 263, 520, 1037])
+def test_edm_strips_every_layout(strategy, pitched, d, N):
+    # rho = 256: 8-row strips of 256 x 256 tiles.  N around the strip (8)
+    # and tile (256) edges; X dense and 16-byte aligned (column points read
+    # as 16-byte chunks) or pitched (one load per coordinate); the full
+    # layout with a pitch that is a multiple of 4 (16-byte stores) and
+    # padding columns that must stay untouched
+    _require_gpu()
+    X = synth.uniform_points(N, d, seed=900 + 10 * N + d)
+    if pitched:
+        Xbig = np.zeros((N, d + 5), dtype=np.float32)
+        Xbig[:, :d] = X
+        Xd = torch.from_numpy(Xbig).cuda()[:, :d]
+    else:
+        Xd = torch.from_numpy(X).cuda()
+    ld = (N + 3) // 4 * 4 + 8
+    F = _full_sentinel(N, ld=ld)
+    tdmap.edm(Xd, layout="full", strategy=strategy, rho=256, out=F, ldd=ld)
+    torch.cuda.synchronize()
+    _check_full(F, X, ld=ld)
+    ref = oedm.edm64_packed(X)
+    for layout, size in (("packed", oedm.tri(N)), ("strict", N * (N - 1) // 2)):
+        buf = torch.empty(size + 64, dtype=torch.float32, device="cuda")
+        buf.view(torch.int32).fill_(int(SENTINEL))
+        tdmap.edm(Xd, layout=layout, strategy=strategy, rho=256, out=buf[:size])
+        torch.cuda.synchronize()
+        got = buf.cpu().numpy()
+        want = ref if layout == "packed" else oedm.edm64_strict(X)
+        _check_rel(got[:size], want, f"{layout} N={N} d={d}")
+        assert np.all(got.view(np.int32)[size:] == SENTINEL), f"{layout}: wrote past the end"
+    # bitwise equal to the paper-style launch (one pair function)
+    R = _full_sentinel(N, ld=ld)
+    tdmap.edm(Xd, layout="full", strategy="ltm", rho=16, out=R, ldd=ld)
+    assert torch.equal(F.view(torch.int32), R.view(torch.int32))
+
+
 @pytest.mark.parametrize("d", [1, 2, 3, 4])
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 31, 64, 1000, 1037, 2900])
 def test_edm_packed_sweep(N, d):
