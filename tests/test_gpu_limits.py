@@ -6,10 +6,10 @@ single HIP launch would pass 2^32 work-items, and packed indices past 2^32.
   boundary, and a row-major succession everywhere in between.
 * N = 93000 points in the packed layout (4,324,546,500 cells, so packed
   positions pass 2^32): the one-cell-per-thread LTM launch needs two
-  launches at every rho in {8, 16, 32}; its output equals the linear sweep's
-  bit for bit, and the sweep (64-bit g(lambda)) is checked against the FP64
-  oracle on rows around both launch boundaries, around position 2^32, and at
-  seeded rows.
+  launches at every rho in {8, 16, 32}; its output, and that of the
+  256-cell strips, equals the linear sweep's bit for bit, and the sweep
+  (64-bit g(lambda)) is checked against the FP64 oracle on rows around both
+  launch boundaries, around position 2^32, and at seeded rows.
 """
 import math
 
@@ -105,6 +105,18 @@ def test_sweep_past_2_32_against_oracle(big_packed):
     for i, e in zip(rows, ref):
         k = oedm.tri(i)
         _check_rel(S[k: k + i + 1].cpu().numpy(), e, f"row {i}")
+
+
+def test_strips_past_2_32_equal_sweep(big_packed):
+    # the 256-cell strips (8-row work-groups, 64-bit packed offsets past
+    # 2^32) write the same bits as the linear sweep
+    X, Xd, S = big_packed
+    C = torch.empty_like(S)
+    tdmap.edm(Xd, layout="packed", strategy="ltm", rho=256, out=C)
+    torch.cuda.synchronize()
+    assert torch.equal(C.view(torch.int32), S.view(torch.int32))
+    del C
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("rho", [8, 16, 32])
