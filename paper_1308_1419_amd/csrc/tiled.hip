@@ -304,23 +304,24 @@ static hipError_t launch_tiled_t(bool bb, const EdmArgs &a) {
     // strips of 256-column tiles for the aligned full layout
     const bool xv = a.ldx == D && (reinterpret_cast<uintptr_t>(a.X) & 15) == 0;
     return xv ? launch_band<D, kLayoutFull, true>(bb, a) : launch_band<D, kLayoutFull, false>(bb, a);
+  } else {
+    const uint64_t nb = (uint64_t)((a.N + TS - 1) / TS);
+    if (bb) {
+      hipLaunchKernelGGL((edm_tile_kernel<TS, D, LAYOUT, VEC, true>),
+                         dim3((uint32_t)nb, (uint32_t)nb), dim3(256), 0, a.stream, a, 0u);
+      return hipGetLastError();
+    }
+    const uint64_t T = nb * (nb + 1) / 2;
+    const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
+    for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
+      const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
+      hipLaunchKernelGGL((edm_tile_kernel<TS, D, LAYOUT, VEC, false>), dim3((uint32_t)c), dim3(256),
+                         0, a.stream, a, (uint32_t)l0);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
-  const uint64_t nb = (uint64_t)((a.N + TS - 1) / TS);
-  if (bb) {
-    hipLaunchKernelGGL((edm_tile_kernel<TS, D, LAYOUT, VEC, true>), dim3((uint32_t)nb, (uint32_t)nb),
-                       dim3(256), 0, a.stream, a, 0u);
-    return hipGetLastError();
-  }
-  const uint64_t T = nb * (nb + 1) / 2;
-  const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
-  for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
-    const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
-    hipLaunchKernelGGL((edm_tile_kernel<TS, D, LAYOUT, VEC, false>), dim3((uint32_t)c), dim3(256), 0,
-                       a.stream, a, (uint32_t)l0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
 }
 
 template <int TS, int D, int LAYOUT>
@@ -328,8 +329,9 @@ static hipError_t launch_tiled_packed(bool bb, const EdmArgs &a) {
   if constexpr (TS == 256) {
     const bool xv = a.ldx == D && (reinterpret_cast<uintptr_t>(a.X) & 15) == 0;
     return xv ? launch_band<D, LAYOUT, true>(bb, a) : launch_band<D, LAYOUT, false>(bb, a);
+  } else {
+    return launch_tiled_t<TS, D, LAYOUT, false>(bb, a);
   }
-  return launch_tiled_t<TS, D, LAYOUT, false>(bb, a);
 }
 
 template <int TS, int D>
