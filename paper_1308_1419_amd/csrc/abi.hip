@@ -326,7 +326,11 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int64
   };
   int ts = rho;
   if (ts == 0) {
-    const TuneKey key(TDMAP_OP_EDM, strategy, layout, d, size_bucket(N));
+    // an output that rules out the 16-byte stores (full layout) or the sweep
+    // (packed layouts) is tuned under its own key
+    const bool aligned = (reinterpret_cast<uintptr_t>(D) & 15) == 0 &&
+                         (layout != TDMAP_FULL || ldd % 4 == 0);
+    const TuneKey key(TDMAP_OP_EDM, strategy, layout + (aligned ? 0 : 64), d, size_bucket(N));
     ts = tuned_lookup(key);
     if (ts == 0) {
       std::vector<int> cands{64, 128, 256};

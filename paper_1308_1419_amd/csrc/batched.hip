@@ -171,18 +171,14 @@ __global__ __launch_bounds__(256) void edm_batched_kernel(const float *__restric
   }
 }
 
-static int g_cu_count = 0;
-
+// Compute units of the current device (queried per launch: no shared state
+// between threads or devices).
 static int cu_count() {
-  if (g_cu_count == 0) {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
-      g_cu_count = n;
-    else
-      g_cu_count = 256;
-  }
-  return g_cu_count;
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+    return n;
+  return 256;
 }
 
 template <int TS, int D>
