@@ -9,6 +9,11 @@
 // Per-tile partial sums then either go to a workspace (deterministic: a
 // second kernel adds them in a fixed order) or are added to dX with
 // atomics.
+//
+// Stress mode (the fused loss and gradient): the tile reads the targets
+// delta_ij instead of dL/dD_ij, forms D_ij itself and uses
+// dL/dD_ij = 2 (D_ij - delta_ij), and also sums the loss
+// sum_{j<i} (D_ij - delta_ij)^2 per tile (to the workspace, or atomically).
 #include "device.h"
 #include "kernels.h"
 
