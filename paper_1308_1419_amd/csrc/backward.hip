@@ -432,12 +432,48 @@ constexpr int bwd_reduce_groups() {
   return 1024 / E >= 4 ? 4 : (1024 / E >= 2 ? 2 : 1);
 }
 
+// Deterministic total of the T per-tile losses by one work-group of NT
+// threads: thread t takes entries t, t + NT, ... into eight accumulators
+// (entry t + NT m into accumulator m mod 8), then a fixed tree over 1024
+// slots (slots past NT hold 0).
+template <int NT>
+__device__ __forceinline__ void loss_total(const float *__restrict__ part, uint64_t count,
+                                           float *__restrict__ loss) {
+  __shared__ float buf[1024];
+  const int t = threadIdx.x;
+  float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  uint64_t e = t;
+  for (; e + 7 * NT < count; e += 8 * NT) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[e + NT * u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += v[u];
+  }
+  for (; e < count; e += NT) acc[0] += part[e];
+  buf[t] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  for (int x = NT + t; x < 1024; x += NT) buf[x] = 0.0f;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    for (int x = t; x < off; x += NT) buf[x] += buf[x + off];
+    __syncthreads();
+  }
+  if (t == 0) loss[0] = buf[0];
+}
+
+// With loss != nullptr (the fused stress pass) one more work-group,
+// blockIdx.x == nb, adds the T per-tile losses.
 template <int TS, int D>
 __global__ __launch_bounds__(TS * D * bwd_reduce_groups<TS * D>()) void edm_bwd_reduce(
-    const float *__restrict__ ws, float *__restrict__ dX, int64_t N, uint32_t nb) {
+    const float *__restrict__ ws, float *__restrict__ dX, int64_t N, uint32_t nb,
+    const float *__restrict__ ws_loss, uint64_t T, float *__restrict__ loss) {
   constexpr int G = bwd_reduce_groups<TS * D>();
   constexpr int E = TS * D;
   const uint32_t B = blockIdx.x;
+  if (B == nb) {
+    loss_total<E * G>(ws_loss, T, loss);
+    return;
+  }
   const int e = threadIdx.x % E;
   const int g = threadIdx.x / E;
   const int64_t p = (int64_t)B * TS + e / D;
@@ -500,7 +536,7 @@ static hipError_t launch_bwd_t(const BwdArgs &a) {
   if (DET) {
     hipLaunchKernelGGL((edm_bwd_reduce<TS, D>), dim3((uint32_t)nb),
                        dim3(TS * D * bwd_reduce_groups<TS * D>()), 0, a.stream, a.ws, a.dX, a.N,
-                       (uint32_t)nb);
+                       (uint32_t)nb, nullptr, (uint64_t)0, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -528,32 +564,6 @@ static hipError_t launch_bwd_ts(const BwdArgs &a) {
   }
 }
 
-// Deterministic total of the per-tile losses: one work-group, thread t
-// takes entries t, t + 1024, ... into eight accumulators (entry t + 1024 m
-// into accumulator m mod 8), then a fixed tree.
-__global__ __launch_bounds__(1024) void stress_loss_reduce(const float *__restrict__ part,
-                                                           uint64_t count, float *__restrict__ loss) {
-  __shared__ float buf[1024];
-  const int t = threadIdx.x;
-  float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  uint64_t e = t;
-  for (; e + 7 * 1024 < count; e += 8 * 1024) {
-    float v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = part[e + 1024 * u];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] += v[u];
-  }
-  for (; e < count; e += 1024) acc[0] += part[e];
-  buf[t] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-  __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
-    if (t < off) buf[t] += buf[t + off];
-    __syncthreads();
-  }
-  if (t == 0) loss[0] = buf[0];
-}
-
 template <int TS, int D, int LAYOUT, bool DET>
 static hipError_t launch_stress_t(const BwdArgs &a) {
   const uint64_t nb = (uint64_t)((a.N + TS - 1) / TS);
@@ -571,11 +581,10 @@ static hipError_t launch_stress_t(const BwdArgs &a) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (DET) {
-    hipLaunchKernelGGL((edm_bwd_reduce<TS, D>), dim3((uint32_t)nb),
+    // nb work-groups for dX and one more for the loss
+    hipLaunchKernelGGL((edm_bwd_reduce<TS, D>), dim3((uint32_t)nb + 1),
                        dim3(TS * D * bwd_reduce_groups<TS * D>()), 0, a.stream, a.ws, a.dX, a.N,
-                       (uint32_t)nb);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(stress_loss_reduce, dim3(1), dim3(1024), 0, a.stream, a.ws_loss, T, a.loss);
+                       (uint32_t)nb, a.ws_loss, T, a.loss);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
