@@ -5,10 +5,11 @@
 // A prologue rounds X to BF16 (round to nearest even), pads the features to
 // a multiple of 16 with zeros and the points to a multiple of 128, and
 // computes the squared norms of the rounded points in FP32.  The main
-// kernel walks the 128 x 128 tiles of the triangle by g(lambda) (Sec. II-A,
-// Eq. (2)); four waves each own a 64 x 64 quadrant computed by 2 x 2
-// v_mfma_f32_32x32x16_bf16 accumulators (BF16 products are exact in FP32,
-// the sums accumulate in FP32).  The epilogue forms
+// kernel walks the triangle by g(lambda) (Sec. II-A, Eq. (2)) on 256 x 256
+// tiles, a work-group taking one row half (two 128 x 128 tiles side by
+// side); each wave owns 32 rows x 128 columns of one of them, computed by
+// four v_mfma_f32_32x32x16_bf16 accumulators (BF16 products are exact in
+// FP32, the sums accumulate in FP32).  The epilogue forms
 // G = n_i + n_j - 2 acc and, when G <= theta (n_i + n_j) (theta = 1/4:
 // the pair is close relative to its norms, where the Gram form cancels),
 // recomputes the distance exactly in FP32 difference form from the FP32
@@ -93,7 +94,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // v_mfma_f32_32x32x16_bf16 accumulators (one per 32-column block).  Its
 // distances go, 16 rows at a time, through a wave-private LDS slice and are
 // written as packed rows with 16-byte stores; no work-group barrier is
-// needed, so the four waves run independently.
+// needed, so the waves run independently.
 //
 // Store layout: a half-wave writes one 128-cell row segment.  Packed row i's
 // segment [col0, col0 + 128) starts sh = (i(i+1)/2 + col0) mod 4 positions
@@ -120,17 +121,28 @@ __device__ __forceinline__ int row_shift(int rr) {
 // are issued before the first product waits (measured: split form 9.5 ->
 // 8.7 ms at N = 100000, d = 64); 0 for any other count.
 template <bool SPLIT, int KPC>
-__global__ __launch_bounds__(256, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs a, uint32_t lam0,
+__global__ __launch_bounds__(512, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs a, uint32_t lam0,
                                                                       uint32_t nblk) {
-  // Each XCD takes one contiguous range of lambda: neighbouring tiles share
+  // Eight waves: the two side-by-side 128 x 128 tiles (I, 2 J2) and
+  // (I, 2 J2 + 1) that form one row half, I = 2 I2 + wg mod 2, of the
+  // 256 x 256 tile (I2, J2) = g(wg / 2), so each row is written as a 1 KB
+  // segment (measured 7.2 -> 7.0 ms, split 8.7 -> 8.4 ms, against one 128 x
+  // 128 tile per work-group; four tiles side by side gave the gain back).
+  // Each XCD takes one contiguous range of wg: neighbouring tiles share
   // the partial 16-byte chunks (and lines) at the ends of their row
   // segments, which then combine in one L2 (measured 9.6 -> 7.2 ms), and
   // they share their BF16 row block.
-  uint32_t I, J;
-  g_lambda(lam0 + xcd_contiguous(blockIdx.x, nblk), I, J);
+  const uint32_t wg = lam0 + xcd_contiguous(blockIdx.x, nblk);
+  uint32_t I2, J2;
+  g_lambda(wg >> 1, I2, J2);
+  const int wl = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint32_t I = 2 * I2 + (wg & 1);
+  uint32_t J = 2 * J2 + (wl >> 2);
   I = __builtin_amdgcn_readfirstlane(I);  // uniform: keep the tile origin scalar
   J = __builtin_amdgcn_readfirstlane(J);
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // the upper right tile of a diagonal 256 x 256 tile, or rows past N
+  if (J > I || (int64_t)I * kGramTile >= a.N) return;
+  const int w = wl & 3;  // the wave's 32-row block of its 128 x 128 tile
   const int l = threadIdx.x & 63;
   const int lr = l & 31;
   const int lk = (l >> 5) * 8;
@@ -190,8 +202,8 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
   // stage row rr holds column c at position c + sh(rr), where sh(rr) is the
   // offset of the packed row past a 16-byte boundary; the stored chunks are
   // then aligned 16-byte LDS reads without bank conflicts
-  __shared__ __align__(16) float stage[4][kGramRows][kGramTile + 4];
-  float(*st)[kGramTile + 4] = stage[w];
+  __shared__ __align__(16) float stage[8][kGramRows][kGramTile + 4];
+  float(*st)[kGramTile + 4] = stage[wl];
   float *__restrict__ out = a.D;
   const int h = l & 31;
   const bool full_rows = !diag && row0 + kGramTile <= N;
@@ -288,7 +300,7 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
 
 template <bool SPLIT>
 static void launch_gram_tiles(int KP, dim3 grid, hipStream_t stream, const GramArgs &a, uint32_t l0) {
-  const dim3 block(256);
+  const dim3 block(512);
   switch (KP) {
     case 16:
       hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 16>), grid, block, 0, stream, a, l0, grid.x);
@@ -329,8 +341,9 @@ hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, 
   if (e != hipSuccess) return e;
   GramArgs a{X, N, d, ldx, Xb, Xlo, nrm, KP, D};
   const uint64_t nb = (uint64_t)(Npad / kGramTile);
-  const uint64_t T = nb * (nb + 1) / 2;
-  const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
+  const uint64_t nb2 = (nb + 1) / 2;
+  const uint64_t T = nb2 * (nb2 + 1);  // two work-groups per 256 x 256 tile
+  const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 512;
   for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
     const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
     if (split)
