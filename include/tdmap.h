@@ -233,9 +233,11 @@ int tdmap_stress_backward(const float *X, int64_t N, int32_t d, int64_t ldx,
  *   point_off  device, S+1 int64, non-decreasing, point_off[0] = 0.
  *   out_off    device, S+1 int64, out_off[s+1] - out_off[s] =
  *              n_s(n_s+1)/2 with n_s = point_off[s+1] - point_off[s].
- *   rho        1: one-cell blocks: a fixed grid sweeps the concatenated
- *              packed output in 4 KB chunks, grid-stride (D_cat 16-byte
- *              aligned);
+ *   rho        1: one-cell blocks: a persistent grid sweeps the
+ *              concatenated packed output; each work-group owns one
+ *              contiguous stretch of 16384-position chunks and reads a set's
+ *              points from LDS (sets of up to 16384 / d points; larger sets
+ *              read global memory);
  *              64 or 128: a persistent grid walks TS x TS tiles in
  *              contiguous ranges;
  *              0: autotuned.
@@ -324,7 +326,8 @@ int tdmap_dummy(int32_t strategy, int32_t variant, int64_t N, int32_t rho, uint3
  * TDMAP_OP_STRESS, and num_sets for TDMAP_OP_BATCHED.  Decisions are cached
  * per (op, strategy, layout, d, ceil(log2(size))); for TDMAP_OP_EDM an
  * output that is not 16-byte aligned (or a full-layout pitch that is not a
- * multiple of 4) is tuned apart, under layout + 64. */
+ * multiple of 4) is tuned apart, under layout + 64, and for
+ * TDMAP_OP_BACKWARD a dD that is not 16-byte aligned under layout 64. */
 int32_t tdmap_tuned_rho(int32_t op, int32_t strategy, int32_t layout, int32_t d, int64_t size);
 
 /* Forget every autotuner decision. */

@@ -367,7 +367,8 @@ int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx, const 
                    det ? reinterpret_cast<float *>(workspace) : nullptr, s};
   int ts = rho;
   if (ts == 0) {
-    const TuneKey key(TDMAP_OP_BACKWARD, 0, 0, d, size_bucket(N));
+    // TS = 256 needs a 16-byte aligned dD: unaligned calls are tuned apart
+    const TuneKey key(TDMAP_OP_BACKWARD, 0, dd_aligned ? 0 : 64, d, size_bucket(N));
     ts = tuned_lookup(key);
     if (ts == 0) {
       std::vector<int> cands{64, 128};
@@ -431,8 +432,6 @@ int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets, const int
   if (num_sets == 0) return TDMAP_OK;
   if (X_cat == nullptr || point_off == nullptr || out_off == nullptr || D_cat == nullptr)
     return TDMAP_ERR_INVALID;
-  const bool aligned = (reinterpret_cast<uintptr_t>(D_cat) & 15) == 0;
-  if (rho == 1 && !aligned) return TDMAP_ERR_UNSUPPORTED;
   if (d > 4) return TDMAP_ERR_UNSUPPORTED;
   const size_t need = tdmap_workspace_size(TDMAP_OP_BATCHED, 0, d, num_sets, rho, 0);
   if (workspace == nullptr || ws_bytes < need) return TDMAP_ERR_WORKSPACE;
@@ -442,7 +441,7 @@ int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets, const int
   // rho = 1: persistent linear sweep of the concatenated packed output;
   // 64 / 128: persistent walk over the prefix-summed tile space
   auto run = [&](int c) {
-    return c == 1 ? tdmap::launch_batched_sweep(a, 64) : tdmap::launch_batched(c, a);
+    return c == 1 ? tdmap::launch_batched_sweep(a) : tdmap::launch_batched(c, a);
   };
   int ts = rho;
   int st = TDMAP_OK;
@@ -450,9 +449,7 @@ int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets, const int
     const TuneKey key(TDMAP_OP_BATCHED, 0, 0, d, size_bucket(num_sets));
     ts = tuned_lookup(key);
     if (ts == 0) {
-      std::vector<int> cands{64, 128};
-      if (aligned) cands.insert(cands.begin(), 1);
-      ts = autotune(cands, s, run, &st);
+      ts = autotune({1, 64, 128}, s, run, &st);
       if (st != TDMAP_OK) return st;
       tuned_store(key, ts);
     }

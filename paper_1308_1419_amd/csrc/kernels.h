@@ -104,8 +104,9 @@ hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, 
 // Packed layout written as a linear sweep (g at one-cell granularity).
 bool sweep_supported(const EdmArgs &a);
 hipError_t launch_sweep(const EdmArgs &a);
-// Batched packed sweep with a persistent grid of wgs_per_cu work-groups per CU.
-hipError_t launch_batched_sweep(const BatchArgs &a, int wgs_per_cu);
+// Batched packed sweep with a persistent grid (two 1024-thread work-groups
+// per CU, each owning one contiguous stretch of the output).
+hipError_t launch_batched_sweep(const BatchArgs &a);
 
 // Fill n floats with a value (a kernel, not a memset, so it can sit in a
 // captured graph).

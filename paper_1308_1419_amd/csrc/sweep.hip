@@ -14,7 +14,9 @@
 // Eq. (10)); row i then holds i cells instead of i + 1.
 //
 // The batched variant sweeps the concatenation of every set's packed
-// triangle; positions past the end of a set continue in the next one.
+// triangle; positions past the end of a set continue in the next one.  Its
+// work-groups each own one contiguous stretch of the output and read the
+// points of a set from LDS.
 #include "device.h"
 #include "kernels.h"
 
@@ -180,14 +182,10 @@ __global__ __launch_bounds__(256) void edm_sweep_kernel(const float *__restrict_
   }
 }
 
-// Batched: positions [0, out_off[S]) of the concatenated packed triangles.
-// Waves take 1024-position chunks in grid-stride order (chunk c, then
-// c + 4 * gridDim.x, ...), so the work-groups in flight always cover one
-// compact window of the output and the few sets it spans stay in cache.
-// The set of a chunk comes from out_off by a galloping search from the
-// wave's previous set; nothing is read on the host.  Chunks inside one set
-// whose first cell lies in a row of at least 1024 cells take the two-row
-// fast path of the single-set sweep; the rest step lane by lane.
+// Batched: the positions [out_off[0], out_off[S]) of the concatenated
+// packed triangles, cut into chunks of kBatchChunk consecutive positions.
+// set_of finds the set holding position e by a galloping search from a set
+// s with out_off[s] <= e; empty sets are skipped.
 __device__ __forceinline__ int32_t set_of(const int64_t *__restrict__ oo, int32_t S, int32_t s,
                                           uint64_t e) {
   if ((uint64_t)oo[s + 1] > e) return s;
@@ -206,96 +204,100 @@ __device__ __forceinline__ int32_t set_of(const int64_t *__restrict__ oo, int32_
   return lo;
 }
 
+// A persistent grid of kBatchWgsPerCu 1024-thread work-groups per CU.
+// Work-group b of G owns chunks [C b / G, C (b + 1) / G) of the C chunks
+// and walks them in address order: every work-group writes one contiguous
+// stretch of the output, and the grid is balanced to one chunk.  A chunk
+// that lies inside one set of at most kBatchLdsFloats / D points reads the
+// set's points from LDS, staged when the walk enters the set, so its loop
+// issues no global load and its stores never wait (vmcnt counts loads and
+// stores alike, and a wait for a load waits for every store issued before
+// it).  Lane l of wave w writes positions c0 + 1024 w + l + 64 q, q < 16:
+// each 4-byte store instruction covers 256 contiguous bytes.  The chunk at
+// the end of a set, and every chunk of a set too large for LDS, map each
+// position on its own (set search and 64-bit g) and read global memory.
+constexpr int kBatchThreads = 1024;
+constexpr int kBatchPer = 16;                           // positions per lane per chunk
+constexpr int kBatchChunk = kBatchThreads * kBatchPer;  // 16384 positions
+constexpr int kBatchLdsFloats = 16384;                  // 64 KB
+constexpr int kBatchWgsPerCu = 2;
+
 template <int D>
-__global__ __launch_bounds__(256) void edm_batched_sweep_kernel(
+__device__ __forceinline__ void lds_pt(const float *xs, uint32_t p, float (&v)[D]) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) v[k] = xs[p * D + k];
+}
+
+template <int D>
+__global__ __launch_bounds__(kBatchThreads, 8) void edm_batched_sweep_kernel(
     const float *__restrict__ X, const int64_t *__restrict__ point_off,
     const int64_t *__restrict__ oo, int32_t S, float *__restrict__ out) {
+  __shared__ float xs[kBatchLdsFloats];
+  const uint64_t first = (uint64_t)oo[0];
   const uint64_t total = (uint64_t)oo[S];
-  const uint64_t chunks = (total + SW_WAVE - 1) / SW_WAVE;
-  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t l = threadIdx.x & 63;
-  int32_t sw = 0;
-  for (uint64_t c = (uint64_t)blockIdx.x * 4 + w; c < chunks; c += (uint64_t)gridDim.x * 4) {
-    const uint64_t ew = c * SW_WAVE;
-    sw = set_of(oo, S, sw, ew);
-    const uint64_t o0 = (uint64_t)oo[sw];
-    const int64_t p0 = point_off[sw];
-    const float *__restrict__ Xs = X + p0 * D;
-    uint64_t iw, jw;
-    g_lambda64(ew - o0, iw, jw);
-    if (iw + 1 >= (uint64_t)SW_WAVE && ew + SW_WAVE <= (uint64_t)oo[sw + 1]) {
-      const int64_t n = point_off[sw + 1] - p0;
-      const uint64_t i1 = iw + 1 < (uint64_t)n ? iw + 1 : iw;
-      float xa[D], xb[D];
-      load_pt<D>(Xs, D, iw, xa);
-      load_pt<D>(Xs, D, i1, xb);
-      float xj[SW_G][4][D];
-      bool lo[SW_G][4];
+  const uint64_t chunks = (total - first + kBatchChunk - 1) / kBatchChunk;
+  const uint64_t G = gridDim.x;
+  const uint64_t c_end = chunks * (blockIdx.x + 1) / G;
+  const uint32_t t = threadIdx.x;
+  const uint32_t off = (t >> 6) * (64 * kBatchPer) + (t & 63);
+  // the set of the current chunk's first position, its output range and
+  // its points (the same values in every thread)
+  int32_t s = 0;
+  uint64_t s_beg = first, s_end = (uint64_t)oo[1];
+  int64_t p0 = point_off[0], n = point_off[1] - point_off[0];
+  int32_t staged = -1;
+  for (uint64_t c = chunks * blockIdx.x / G; c < c_end; ++c) {
+    const uint64_t c0 = first + c * kBatchChunk;
+    if (c0 >= s_end) {
+      s = set_of(oo, S, s, c0);
+      s_beg = (uint64_t)oo[s];
+      s_end = (uint64_t)oo[s + 1];
+      p0 = point_off[s];
+      n = point_off[s + 1] - p0;
+    }
+    if (c0 + kBatchChunk <= s_end && n <= kBatchLdsFloats / D) {
+      if (staged != s) {
+        __syncthreads();  // every wave is done with the previous set
+        const float *__restrict__ Xs = X + p0 * D;
+        for (int e = (int)t; e < (int)n * D; e += kBatchThreads) xs[e] = Xs[e];
+        __syncthreads();
+        staged = s;
+      }
+      // lambda < n(n+1)/2 <= 2^27 here: the 32-bit map
+      uint32_t i, j;
+      g_lambda((uint32_t)(c0 - s_beg) + off, i, j);
+      float xi[D], xj[D];
+      lds_pt<D>(xs, i, xi);
 #pragma unroll
-      for (int g = 0; g < SW_G; ++g)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          // columns are below the set's size n, and n * D * 4 < 2^32: a set
-          // that large would need n(n+1)/2 > 2^53 output cells
-          const uint32_t j = (uint32_t)jw + 256 * g + 4 * l + q;
-          lo[g][q] = j <= (uint32_t)iw;
-          load_pt32<D>(Xs, D * 4u, lo[g][q] ? j : j - (uint32_t)iw - 1, xj[g][q]);
+      for (int q = 0; q < kBatchPer; ++q) {
+        if (q > 0) {
+          j += 64;
+          if (j > i) {
+            do {
+              j -= i + 1;
+              ++i;
+            } while (j > i);
+            lds_pt<D>(xs, i, xi);
+          }
         }
-#pragma unroll
-      for (int g = 0; g < SW_G; ++g) {
-        f4 o;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          float xi[D];
-#pragma unroll
-          for (int k = 0; k < D; ++k) xi[k] = lo[g][q] ? xa[k] : xb[k];
-          o[q] = pair_dist<D>(xi, xj[g][q]);
-        }
-        __builtin_nontemporal_store(o, reinterpret_cast<f4 *>(out + ew + 256 * g + 4 * l));
+        lds_pt<D>(xs, j, xj);
+        __builtin_nontemporal_store(pair_dist<D>(xi, xj), out + c0 + off + 64 * q);
       }
       continue;
     }
-    // general path: lane by lane, crossing rows and sets
-    for (int g = 0; g < SW_G; ++g) {
-      const uint64_t e0 = ew + 256 * g + 4 * l;
-      if (e0 >= total) break;
-      int32_t s = sw;
-      while ((uint64_t)oo[s + 1] <= e0) ++s;
+#pragma unroll 1
+    for (int q = 0; q < kBatchPer; ++q) {
+      const uint64_t e = c0 + off + 64 * q;
+      if (e >= total) break;
+      int32_t sl = s;
+      while ((uint64_t)oo[sl + 1] <= e) ++sl;
       uint64_t i, j;
-      g_lambda64(e0 - (uint64_t)oo[s], i, j);
-      int64_t n = point_off[s + 1] - point_off[s];
-      const float *__restrict__ Xl = X + point_off[s] * D;
-      float xi[D];
+      g_lambda64(e - (uint64_t)oo[sl], i, j);
+      const float *__restrict__ Xl = X + point_off[sl] * D;
+      float xi[D], xj[D];
       load_pt<D>(Xl, D, i, xi);
-      float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (e0 + q >= total) break;
-        if (j > i) {
-          ++i;
-          j = 0;
-          if ((int64_t)i >= n) {  // first row of the next non-empty set
-            do {
-              ++s;
-            } while ((uint64_t)oo[s + 1] <= e0 + q);
-            i = 0;
-            n = point_off[s + 1] - point_off[s];
-            Xl = X + point_off[s] * D;
-          }
-          load_pt<D>(Xl, D, i, xi);
-        }
-        float xj[D];
-        load_pt<D>(Xl, D, j, xj);
-        v[q] = pair_dist<D>(xi, xj);
-        ++j;
-      }
-      if (e0 + 4 <= total) {
-        f4 o = {v[0], v[1], v[2], v[3]};
-        __builtin_nontemporal_store(o, reinterpret_cast<f4 *>(out + e0));
-      } else {
-        for (int q = 0; q < 4; ++q)
-          if (e0 + q < total) __builtin_nontemporal_store(v[q], out + e0 + q);
-      }
+      load_pt<D>(Xl, D, j, xj);
+      __builtin_nontemporal_store(pair_dist<D>(xi, xj), out + e);
     }
   }
 }
@@ -340,21 +342,16 @@ hipError_t launch_sweep(const EdmArgs &a) {
   }
 }
 
-static int g_sweep_cus = 0;
-
-hipError_t launch_batched_sweep(const BatchArgs &a, int wgs_per_cu) {
+hipError_t launch_batched_sweep(const BatchArgs &a) {
   if (a.num_sets == 0) return hipSuccess;
-  if (g_sweep_cus == 0) {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
-      g_sweep_cus = n;
-    else
-      g_sweep_cus = 256;
-  }
-  const dim3 grid((uint32_t)(g_sweep_cus * wgs_per_cu));
-#define TD_BSWEEP(DD)                                                                      \
-  hipLaunchKernelGGL(edm_batched_sweep_kernel<DD>, grid, dim3(256), 0, a.stream, a.X,     \
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  const dim3 grid((uint32_t)(cus * kBatchWgsPerCu));
+#define TD_BSWEEP(DD)                                                                          \
+  hipLaunchKernelGGL(edm_batched_sweep_kernel<DD>, grid, dim3(kBatchThreads), 0, a.stream, a.X, \
                      a.point_off, a.out_off, a.num_sets, a.D)
   switch (a.d) {
     case 1: TD_BSWEEP(1); break;

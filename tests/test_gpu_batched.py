@@ -98,6 +98,58 @@ def test_batched_many_small_sets(rho):
     assert np.all(got.view(np.int32)[len(ref):] == SENTINEL)
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_batched_sets_beyond_lds(d):
+    # the linear sweep stages a set's points in 64 KB of LDS (16384 / d
+    # points); a larger set, and the chunk at the end of every set, take the
+    # path that maps each position on its own and reads global memory.
+    # Sets at the cap, one past it and far past it, between small and empty
+    # ones; every walk writes the same bits as the tiles.
+    _require_gpu()
+    cap = 16384 // d
+    big = cap + 1 if d > 1 else 2 * cap + 3
+    sizes = [300, big, 0, 1, cap, 777, 2, big + 10, 9]
+    X, po, oo, buf = _run(sizes, d, 1, seed=40 + d)
+    total = int(oo[-1])
+    assert np.all(buf.cpu().numpy().view(np.int32)[total:] == SENTINEL), "wrote past the last set"
+    Xd = torch.from_numpy(X).cuda()
+    other = torch.empty(total, dtype=torch.float32, device="cuda")
+    tdmap.edm_batched(Xd, torch.from_numpy(po).cuda(), torch.from_numpy(oo).cuda(), rho=64, out=other)
+    torch.cuda.synchronize()
+    assert torch.equal(other.view(torch.int32), buf[:total].view(torch.int32))
+    for s, n in enumerate(sizes):
+        if n == 0:
+            continue
+        pts = X[po[s]: po[s + 1]]
+        rows = range(n) if n <= 2000 else sorted({0, 1, n // 3, n // 2, n - 2, n - 1}
+                                                  | set(range(cap - 3, min(cap + 3, n))))
+        ref = native.edm_rows(pts, rows)
+        for r, row in zip(rows, ref):
+            a = int(oo[s]) + r * (r + 1) // 2
+            _check_rel(buf[a: a + r + 1].cpu().numpy(), row, f"d={d} set {s} (n={n}) row {r}")
+
+
+def test_batched_unaligned_output():
+    # every walk takes an output at any 4-byte offset; the tuner's choice
+    # is shared by aligned and unaligned calls
+    _require_gpu()
+    sizes = [700, 3, 0, 1500, 64]
+    X, po, oo, buf = _run(sizes, 3, 64, seed=77)
+    total = int(oo[-1])
+    Xd = torch.from_numpy(X).cuda()
+    pod, ood = torch.from_numpy(po).cuda(), torch.from_numpy(oo).cuda()
+    for rho in (1, 64, 128, 0):
+        for shift in (1, 2, 3):
+            other = torch.empty(total + 8, dtype=torch.float32, device="cuda")
+            other.view(torch.int32).fill_(SENTINEL)
+            tdmap.edm_batched(Xd, pod, ood, rho=rho, out=other[shift: shift + total])
+            torch.cuda.synchronize()
+            assert torch.equal(other[shift: shift + total].view(torch.int32),
+                               buf[:total].view(torch.int32)), (rho, shift)
+            bits = other.view(torch.int32)
+            assert bool(torch.all(bits[:shift] == SENTINEL)) and bool(torch.all(bits[shift + total:] == SENTINEL))
+
+
 def test_batched_workload_full_size():
     # the 4096-set workload (n uniform in [64, 4096]); 256 seeded sets plus
     # the smallest and the largest are compared with the C oracle, every
