@@ -74,12 +74,14 @@ def test_batched_ragged_sets(rho, d):
         assert torch.equal(one.view(torch.int32), buf[oo[s]: oo[s + 1]].view(torch.int32)), s
 
 
-def test_batched_empty_and_single():
+@pytest.mark.parametrize("rho", [1, 64, 128])
+def test_batched_empty_and_single(rho):
     _require_gpu()
-    X, po, oo, buf = _run([0, 0, 0], 3, 64, seed=1)
+    X, po, oo, buf = _run([0, 0, 0], 3, rho, seed=1)
     assert np.all(buf.cpu().numpy().view(np.int32) == SENTINEL)
-    X, po, oo, buf = _run([1], 3, 128, seed=2)
+    X, po, oo, buf = _run([1], 3, rho, seed=2)
     assert buf[0].item() == 0.0
+    assert np.all(buf.cpu().numpy().view(np.int32)[1:] == SENTINEL)
     # no sets at all is a no-op
     tdmap.tdmap_edm_batched(0, 3, 0, 0, 0, 0, 64, 0, 0, 0)
 
@@ -107,11 +109,10 @@ def test_batched_sets_beyond_lds(d):
     # ones; every walk writes the same bits as the tiles.
     _require_gpu()
     cap = 16384 // d
-    big = cap + 1 if d > 1 else 2 * cap + 3
-    sizes = [300, big, 0, 1, cap, 777, 2, big + 10, 9]
+    sizes = [300, cap + 1, 0, 1, cap, 777, 2, cap + 1000, 9]
     X, po, oo, buf = _run(sizes, d, 1, seed=40 + d)
     total = int(oo[-1])
-    assert np.all(buf.cpu().numpy().view(np.int32)[total:] == SENTINEL), "wrote past the last set"
+    assert bool(torch.all(buf.view(torch.int32)[total:] == SENTINEL)), "wrote past the last set"
     Xd = torch.from_numpy(X).cuda()
     other = torch.empty(total, dtype=torch.float32, device="cuda")
     tdmap.edm_batched(Xd, torch.from_numpy(po).cuda(), torch.from_numpy(oo).cuda(), rho=64, out=other)
