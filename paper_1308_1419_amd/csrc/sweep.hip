@@ -223,9 +223,9 @@ constexpr int kBatchLdsFloats = 16384;                  // 64 KB
 constexpr int kBatchWgsPerCu = 2;
 
 template <int D>
-__device__ __forceinline__ void lds_pt(const float *xs, uint32_t p, float (&v)[D]) {
+__device__ __forceinline__ void lds_pt(const float *p, float (&v)[D]) {
 #pragma unroll
-  for (int k = 0; k < D; ++k) v[k] = xs[p * D + k];
+  for (int k = 0; k < D; ++k) v[k] = p[k];
 }
 
 template <int D>
@@ -263,24 +263,27 @@ __global__ __launch_bounds__(kBatchThreads, 8) void edm_batched_sweep_kernel(
         __syncthreads();
         staged = s;
       }
-      // lambda < n(n+1)/2 <= 2^27 here: the 32-bit map
+      // lambda < n(n+1)/2 <= 2^27 here: the 32-bit map.  The walk keeps
+      // the LDS offsets iD = i D and jD = j D (additions only; j > i is
+      // jD > iD, and a row of i + 1 cells is (i + 1) D floats).
       uint32_t i, j;
       g_lambda((uint32_t)(c0 - s_beg) + off, i, j);
+      uint32_t iD = i * D, jD = j * D;
       float xi[D], xj[D];
-      lds_pt<D>(xs, i, xi);
+      lds_pt<D>(xs + iD, xi);
 #pragma unroll
       for (int q = 0; q < kBatchPer; ++q) {
         if (q > 0) {
-          j += 64;
-          if (j > i) {
+          jD += 64 * D;
+          if (jD > iD) {
             do {
-              j -= i + 1;
-              ++i;
-            } while (j > i);
-            lds_pt<D>(xs, i, xi);
+              iD += D;
+              jD -= iD;
+            } while (jD > iD);
+            lds_pt<D>(xs + iD, xi);
           }
         }
-        lds_pt<D>(xs, j, xj);
+        lds_pt<D>(xs + jD, xj);
         __builtin_nontemporal_store(pair_dist<D>(xi, xj), out + c0 + off + 64 * q);
       }
       continue;
