@@ -322,7 +322,8 @@ int tdmap_dummy(int32_t strategy, int32_t variant, int64_t N, int32_t rho, uint3
 /* Tile edge the autotuner has chosen for a call with rho = 0, or 0 if that
  * configuration has not been tuned yet.  `strategy` and `layout` are those
  * of the call (ignored for TDMAP_OP_BACKWARD, TDMAP_OP_STRESS and
- * TDMAP_OP_BATCHED); `size` is N for TDMAP_OP_EDM, TDMAP_OP_BACKWARD and
+ * TDMAP_OP_BATCHED, except layout 64 for TDMAP_OP_BACKWARD, below); `size`
+ * is N for TDMAP_OP_EDM, TDMAP_OP_BACKWARD and
  * TDMAP_OP_STRESS, and num_sets for TDMAP_OP_BATCHED.  Decisions are cached
  * per (op, strategy, layout, d, ceil(log2(size))); for TDMAP_OP_EDM an
  * output that is not 16-byte aligned (or a full-layout pitch that is not a

@@ -223,7 +223,8 @@ void tdmap_autotune_reset(void) {
 }
 
 int32_t tdmap_tuned_rho(int32_t op, int32_t strategy, int32_t layout, int32_t d, int64_t size) {
-  if (op != TDMAP_OP_EDM) strategy = layout = 0;
+  if (op != TDMAP_OP_EDM) strategy = 0;
+  if (op != TDMAP_OP_EDM && !(op == TDMAP_OP_BACKWARD && layout == 64)) layout = 0;
   return tuned_lookup(TuneKey(op, strategy, layout, d, size_bucket(size)));
 }
 

@@ -111,6 +111,28 @@ def test_backward_unaligned_dD_pointer():
     _check_grad(got.cpu().numpy(), oedm.edm_backward64(X, dD), "unaligned dD")
 
 
+def test_backward_tuned_apart_by_alignment():
+    # the tuner keeps separate decisions for aligned and unaligned dD, so a
+    # 16-byte-load tile chosen for one is never replayed on the other
+    _require_gpu()
+    N, d = 900, 3
+    X = synth.uniform_points(N, d, seed=15)
+    dD = np.random.default_rng(7).standard_normal(oedm.tri(N)).astype(np.float32)
+    buf = torch.empty(oedm.tri(N) + 4, dtype=torch.float32, device="cuda")
+    Xd = torch.from_numpy(X).cuda()
+    tdmap.tdmap_autotune_reset()
+    buf[: oedm.tri(N)] = torch.from_numpy(dD).cuda()
+    tdmap.edm_backward(Xd, buf[: oedm.tri(N)], rho=0, deterministic=True)
+    torch.cuda.synchronize()
+    assert tdmap.tdmap_tuned_rho(tdmap.OP_BACKWARD, 0, 0, d, N) in (64, 128, 256)
+    assert tdmap.tdmap_tuned_rho(tdmap.OP_BACKWARD, 0, 64, d, N) == 0
+    buf[1: oedm.tri(N) + 1] = torch.from_numpy(dD).cuda()
+    got = tdmap.edm_backward(Xd, buf[1: oedm.tri(N) + 1], rho=0, deterministic=True)
+    torch.cuda.synchronize()
+    assert tdmap.tdmap_tuned_rho(tdmap.OP_BACKWARD, 0, 64, d, N) in (64, 128)
+    _check_grad(got.cpu().numpy(), oedm.edm_backward64(X, dD), "unaligned dD after an aligned tune")
+
+
 def test_backward_coincident_points_and_zero_gradient():
     _require_gpu()
     X = synth.uniform_points(200, 3, seed=6)
