@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kBatchThreads, 8) void edm_batched_sweep_kernel(
         __syncthreads();
         staged = s;
       }
-      // lambda < n(n+1)/2 <= 2^27 here: the 32-bit map.  The walk keeps
+      // lambda < n(n+1)/2 < 2^28 here: the 32-bit map.  The walk keeps
       // the LDS offsets iD = i D and jD = j D (additions only; j > i is
       // jD > iD, and a row of i + 1 cells is (i + 1) D floats).
       uint32_t i, j;
