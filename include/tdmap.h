@@ -232,7 +232,9 @@ int tdmap_stress_backward(const float *X, int64_t N, int32_t d, int64_t ldx,
  *   X_cat      device, (point_off[S]) x d FP32, pitch d.
  *   point_off  device, S+1 int64, non-decreasing, point_off[0] = 0.
  *   out_off    device, S+1 int64, out_off[s+1] - out_off[s] =
- *              n_s(n_s+1)/2 with n_s = point_off[s+1] - point_off[s].
+ *              n_s(n_s+1)/2 with n_s = point_off[s+1] - point_off[s];
+ *              out_off[0] may be above 0 (D_cat[0 .. out_off[0]) is not
+ *              written).
  *   rho        1: one-cell blocks: a persistent grid sweeps the
  *              concatenated packed output; each work-group owns one
  *              contiguous stretch of 16384-position chunks and reads a set's

@@ -151,6 +151,35 @@ def test_batched_unaligned_output():
             assert bool(torch.all(bits[:shift] == SENTINEL)) and bool(torch.all(bits[shift + total:] == SENTINEL))
 
 
+def test_batched_output_offsets_not_from_zero():
+    # out_off[0] > 0: set 0 starts inside D_cat; every walk writes exactly
+    # [out_off[0], out_off[S]) and agrees bitwise
+    _require_gpu()
+    sizes = np.array([900, 0, 5, 1300], dtype=np.int64)
+    rng = np.random.default_rng(21)
+    po = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    shift = 37
+    oo = (shift + np.concatenate([[0], np.cumsum(sizes * (sizes + 1) // 2)])).astype(np.int64)
+    X = rng.random((int(po[-1]), 3), dtype=np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    pod, ood = torch.from_numpy(po).cuda(), torch.from_numpy(oo).cuda()
+    total = int(oo[-1])
+    ref = oedm.edm64_batched(X, po)
+    first = None
+    for rho in (1, 64, 128):
+        buf = torch.empty(total + 64, dtype=torch.float32, device="cuda")
+        buf.view(torch.int32).fill_(SENTINEL)
+        tdmap.edm_batched(Xd, pod, ood, rho=rho, out=buf[:total])
+        torch.cuda.synchronize()
+        bits = buf.view(torch.int32)
+        assert bool(torch.all(bits[:shift] == SENTINEL)), f"rho={rho} wrote before out_off[0]"
+        assert bool(torch.all(bits[total:] == SENTINEL)), f"rho={rho} wrote past the last set"
+        _check_rel(buf[shift:total].cpu().numpy(), ref, f"rho={rho}")
+        if first is None:
+            first = bits[:total].clone()
+        assert torch.equal(bits[:total], first), rho
+
+
 def test_batched_workload_full_size():
     # the 4096-set workload (n uniform in [64, 4096]); 256 seeded sets plus
     # the smallest and the largest are compared with the C oracle, every
