@@ -68,6 +68,8 @@ def _load() -> ctypes.CDLL:
         "tdmap_stress_backward": ([vp, i64, i32, i64, vp, i64, i32, vp, vp, i32, i32, vp, sz,
                                    vp], ctypes.c_int),
         "tdmap_edm_batched": ([vp, i32, i32, vp, vp, vp, i32, vp, sz, vp], ctypes.c_int),
+        "tdmap_gram_recompute_count": ([vp, i64, i32, i64, vp, i32, i32, vp, sz, vp, vp],
+                                       ctypes.c_int),
         "tdmap_workspace_size": ([i32, i64, i32, i32, i32, i32], sz),
         "tdmap_waste_counts": ([i32, i64, i32, vp], ctypes.c_int),
         "tdmap_count_waste": ([i32, i64, i32, vp, vp], ctypes.c_int),
@@ -88,7 +90,7 @@ def _load() -> ctypes.CDLL:
 
 EXPORTED = (
     "tdmap_map_blocks", "tdmap_map_blocks_nodiag", "tdmap_edm", "tdmap_edm_backward",
-    "tdmap_stress_backward", "tdmap_edm_batched",
+    "tdmap_stress_backward", "tdmap_edm_batched", "tdmap_gram_recompute_count",
     "tdmap_workspace_size", "tdmap_waste_counts", "tdmap_count_waste",
     "tdmap_map_blocks_variant", "tdmap_dummy", "tdmap_stream_fill",
     "tdmap_tuned_rho", "tdmap_autotune_reset", "tdmap_status_string",
@@ -152,6 +154,14 @@ def tdmap_edm_batched(X_cat: int, d: int, num_sets: int, point_off: int, out_off
                       stream: int) -> None:
     _check(_load().tdmap_edm_batched(X_cat, d, num_sets, point_off, out_off, D_cat, rho,
                                      workspace, ws_bytes, stream), "tdmap_edm_batched")
+
+
+def tdmap_gram_recompute_count(X: int, N: int, d: int, ldx: int, D: int, precision: int,
+                               rho: int, workspace: int, ws_bytes: int, count: int,
+                               stream: int) -> None:
+    _check(_load().tdmap_gram_recompute_count(X, N, d, ldx, D, precision, rho, workspace,
+                                              ws_bytes, count, stream),
+           "tdmap_gram_recompute_count")
 
 
 def tdmap_workspace_size(op: int, N: int, d: int, num_sets: int, rho: int, flags: int) -> int:
@@ -218,6 +228,50 @@ def _points(X):
     return X
 
 
+def _device_tensor(t, name: str, dtype, device, min_numel: int = 0,
+                   numel: Optional[int] = None):
+    """Host-side checks of a tensor argument that needs no synchronisation:
+    type, dtype, device, contiguity and size.  A wrong dtype or a short
+    buffer would otherwise make a kernel read or write out of bounds."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda or t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} elements, got {t.numel()}")
+    if t.numel() < min_numel:
+        raise ValueError(f"{name} must hold at least {min_numel} elements, got {t.numel()}")
+    return t
+
+
+def _triangle_cells(N: int, layout: int) -> int:
+    """Elements a packed or strict output of N points holds."""
+    return strict_size(N) if layout == PACKED_STRICT else packed_size(N)
+
+
+def _check_full_buffer(t, name: str, N: int, ldd: int, device):
+    """A full-layout buffer: float32 on the device with room for N rows of
+    pitch ldd (the last row needs N cells)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32:
+        raise TypeError(f"{name} must be a float32 tensor")
+    if not t.is_cuda or t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if ldd < N:
+        raise ValueError(f"{name}: row pitch {ldd} is below N = {N}")
+    need = (N - 1) * ldd + N if N > 0 else 0
+    if t.dim() == 2:
+        if t.stride(1) != 1 or t.stride(0) != ldd or t.shape[0] < N or t.shape[1] < N:
+            raise ValueError(f"{name}: expected at least {N} x {N} with row pitch {ldd}")
+    elif not (t.is_contiguous() and t.numel() >= need):
+        raise ValueError(f"{name} must be contiguous with at least {need} elements")
+
+
 def packed_size(N: int) -> int:
     return N * (N + 1) // 2
 
@@ -280,6 +334,11 @@ def edm(X, layout: str = "full", strategy: str = "ltm", rho: int = 0,
             out = torch.empty(packed_size(N), dtype=torch.float32, device=X.device)
     if ldd is None:
         ldd = out.stride(0) if lay == FULL else 0
+    if lay == FULL:
+        _check_full_buffer(out, "out", N, ldd, X.device)
+    else:
+        _device_tensor(out, "out", torch.float32, X.device,
+                       min_numel=_triangle_cells(N, lay))
     ws_bytes = tdmap_workspace_size(OP_EDM, N, d, 0, rho, prec)
     if ws_bytes and workspace is None:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=X.device)
@@ -288,6 +347,29 @@ def edm(X, layout: str = "full", strategy: str = "ltm", rho: int = 0,
     tdmap_edm(X.data_ptr(), N, d, X.stride(0), out.data_ptr(), ldd, lay,
               STRATEGIES[strategy], rho, prec, ws_ptr, ws_len, _stream())
     return out
+
+
+def gram_recompute_count(X, precision: str = "bf16_gram", rho: int = 0, out=None,
+                         workspace=None):
+    """(D, count): the packed Gram-form EDM of X and the number of pairs
+    j <= i that took the FP32 recompute (see tdmap_gram_recompute_count);
+    ``count`` is a one-element int64 CUDA tensor holding the uint64 bits."""
+    torch = _torch()
+    X = _points(X)
+    N, d = X.shape
+    prec = PRECISIONS[precision]
+    if out is None:
+        out = torch.empty(packed_size(N), dtype=torch.float32, device=X.device)
+    _device_tensor(out, "out", torch.float32, X.device, min_numel=packed_size(N))
+    ws_bytes = tdmap_workspace_size(OP_EDM, N, d, 0, rho, prec)
+    if ws_bytes and workspace is None:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=X.device)
+    ws_ptr = workspace.data_ptr() if workspace is not None else 0
+    ws_len = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    count = torch.empty(1, dtype=torch.int64, device=X.device)
+    tdmap_gram_recompute_count(X.data_ptr(), N, d, X.stride(0), out.data_ptr(), prec, rho,
+                               ws_ptr, ws_len, count.data_ptr(), _stream())
+    return out, count
 
 
 def edm_backward(X, dD, layout: str = "packed", rho: int = 0, deterministic: bool = True,
@@ -299,8 +381,13 @@ def edm_backward(X, dD, layout: str = "packed", rho: int = 0, deterministic: boo
     lay = LAYOUTS[layout]
     if out is None:
         out = torch.empty((N, d), dtype=torch.float32, device=X.device)
+    _device_tensor(out, "out", torch.float32, X.device, numel=N * d)
     if ldd is None:
         ldd = dD.stride(0) if lay == FULL else 0
+    if lay == FULL:
+        _check_full_buffer(dD, "dD", N, ldd, X.device)
+    else:
+        _device_tensor(dD, "dD", torch.float32, X.device, min_numel=_triangle_cells(N, lay))
     det = 1 if deterministic else 0
     ws_bytes = tdmap_workspace_size(OP_BACKWARD, N, d, 0, rho, det)
     if ws_bytes and workspace is None:
@@ -325,8 +412,15 @@ def stress_backward(X, delta, layout: str = "packed", rho: int = 0,
         out = torch.empty((N, d), dtype=torch.float32, device=X.device)
     if loss is None:
         loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    _device_tensor(out, "out", torch.float32, X.device, numel=N * d)
+    _device_tensor(loss, "loss", torch.float32, X.device, min_numel=1)
     if ldd is None:
         ldd = delta.stride(0) if lay == FULL else 0
+    if lay == FULL:
+        _check_full_buffer(delta, "delta", N, ldd, X.device)
+    else:
+        _device_tensor(delta, "delta", torch.float32, X.device,
+                       min_numel=_triangle_cells(N, lay))
     det = 1 if deterministic else 0
     ws_bytes = tdmap_workspace_size(OP_STRESS, N, d, 0, rho, det)
     if ws_bytes and workspace is None:
@@ -350,9 +444,16 @@ def edm_batched(X_cat, point_off, out_off, rho: int = 0, out=None, workspace=Non
     if X_cat.stride(0) != d:
         raise ValueError("X_cat must be contiguous")
     S = point_off.numel() - 1
+    if S < 0:
+        raise ValueError("point_off must hold S+1 offsets")
+    _device_tensor(point_off, "point_off", torch.int64, X_cat.device)
+    _device_tensor(out_off, "out_off", torch.int64, X_cat.device, numel=S + 1)
     if out is None:
         total = int(out_off[-1].item())
         out = torch.empty(total, dtype=torch.float32, device=X_cat.device)
+    # the size of out against out_off[S] would need a synchronising read of
+    # the device offsets: only its type, device and contiguity are checked
+    _device_tensor(out, "out", torch.float32, X_cat.device)
     ws_bytes = tdmap_workspace_size(OP_BATCHED, 0, d, S, rho, 0)
     if ws_bytes and workspace is None:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=X_cat.device)
@@ -384,8 +485,13 @@ def _make_autograd():
 
         @staticmethod
         def forward(ctx, X, rho: int = 0, deterministic: bool = True):
+            if rho not in FORWARD_RHOS:
+                raise ValueError(f"rho must be one of {FORWARD_RHOS}, got {rho}")
             ctx.save_for_backward(X)
-            ctx.rho = rho
+            # the backward tiles are 64, 128 or 256 cells wide; a forward
+            # block size it has no tile for (the one-cell sweep, the paper's
+            # 8 / 16 / 32 blocks) leaves the backward to the autotuner
+            ctx.rho = rho if rho in BACKWARD_RHOS else 0
             ctx.deterministic = deterministic
             return edm(X.contiguous(), layout="packed", strategy="ltm", rho=rho)
 
@@ -398,6 +504,10 @@ def _make_autograd():
 
     return EDM
 
+
+# block sizes of the packed forward and of the backward (tdmap.h)
+FORWARD_RHOS = (0, 1, 8, 16, 32, 64, 128, 256)
+BACKWARD_RHOS = (0, 64, 128, 256)
 
 _EDM = None
 

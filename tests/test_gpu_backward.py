@@ -169,6 +169,33 @@ def test_autograd_stress_small_matches_fp64():
     _check_grad(Xt.grad.cpu().numpy(), g64, "autograd n=64")
 
 
+@pytest.mark.parametrize("rho", [1, 16, 64, 256])
+def test_autograd_forward_block_sizes(rho):
+    # any forward block size runs its backward: sizes the backward has no
+    # tile for (the one-cell sweep, the paper's 16 x 16 blocks) fall back to
+    # the autotuned backward tile
+    _require_gpu()
+    X, Xp = synth.stress_inputs(64, 3, seed=synth.workload_seed(4))
+    delta = oedm.edm64_packed(Xp)
+    L64, g64 = oedm.stress_grad64(X, delta)
+    EDM = tdmap.EDM()
+    Xt = torch.from_numpy(X).cuda().requires_grad_(True)
+    dl = torch.from_numpy(delta.astype(np.float32)).cuda()
+    D = EDM.apply(Xt, rho)
+    L = ((D - dl) ** 2).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    assert abs(float(L.detach()) - L64) <= 1e-5 * L64
+    _check_grad(Xt.grad.cpu().numpy(), g64, f"autograd rho={rho}")
+
+
+def test_autograd_rejects_unknown_block_size():
+    _require_gpu()
+    Xt = torch.zeros((8, 3), dtype=torch.float32, device="cuda", requires_grad=True)
+    with pytest.raises(ValueError):
+        tdmap.EDM().apply(Xt, 12)
+
+
 def _stress_fp64(Z, delta):
     N = Z.shape[0]
     tot = 0.0
