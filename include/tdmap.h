@@ -145,8 +145,15 @@ int tdmap_map_blocks_nodiag(uint64_t lambda0, uint64_t count, uint32_t *ij, void
  *                          first call for a (layout, strategy, d, size)
  *                          class.
  *   precision TDMAP_FP32 for every strategy; TDMAP_BF16_GRAM and
- *            TDMAP_BF16X3_GRAM only with TDMAP_LTM, TDMAP_PACKED and rho = 0
- *            or 128.  Their error per pair that is not recomputed is at most
+ *            TDMAP_BF16X3_GRAM only with TDMAP_LTM, TDMAP_PACKED and rho = 0,
+ *            128 or 256 (128: eight-wave work-groups, each over two 128 x 128
+ *            tiles side by side; 256: four-wave work-groups, each over a
+ *            32-row strip of a 256 x 256 tile, the strips of a tile row taken
+ *            strip by strip across the row; 0: the autotuner's choice
+ *            between the two).  Both kernels compute every 32 x 32 block with
+ *            the same MFMA products in the same order, so their outputs are
+ *            bitwise identical.  D may start at any 4-byte boundary.  Their
+ *            error per pair that is not recomputed is at most
  *            r (|x_i| + |x_j|) + E / (D - r (|x_i| + |x_j|)) + 4 u32 D with
  *            r = 2^-8 (BF16) or 2^-16 (BF16X3), u32 = 2^-24 and E the FP32
  *            accumulation bound 2 (m d + 4) u32 (|x_i|^2 + |x_j|^2)(1 + 2^-8)^2
@@ -171,6 +178,23 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx,
               float *D, int64_t ldd, int32_t layout, int32_t strategy,
               int32_t rho, int32_t precision,
               void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Instrumented Gram-form EDM: the launch tdmap_edm makes for the same
+ * arguments (precision TDMAP_BF16_GRAM or TDMAP_BF16X3_GRAM, layout
+ * TDMAP_PACKED, strategy TDMAP_LTM; rho 128 or 256 picks the kernel, 0 the
+ * autotuner's choice, or 256 if that configuration is not tuned yet), with
+ * the same output, that also counts the pairs (i, j), j <= i < N, which took
+ * the FP32 difference-form recompute (G <= (n_i + n_j)/4).  It reports the
+ * size of the recompute path on a workload; it is a separate build of the
+ * kernel (one atomic add per wave that recomputes), never the one timed.
+ *   count  device, one uint64, overwritten.
+ * Other arguments and errors as for tdmap_edm; INVALID for a NULL count.
+ */
+int tdmap_gram_recompute_count(const float *X, int64_t N, int32_t d, int64_t ldx,
+                               float *D, int32_t precision, int32_t rho,
+                               void *workspace, size_t ws_bytes, uint64_t *count,
+                               void *stream);
 
 /*
  * Gradient through the EDM: given dD_ij = dL/dD_ij for the cells of the
@@ -208,7 +232,7 @@ int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx,
  *          upper triangle of the full layout are not read into the sum.
  *   dX     device, N x d FP32, row pitch d, overwritten.
  *   loss   device, one FP32, overwritten with L (0 when N <= 1).
- *   rho    tile edge: 0 (autotuned), 64 or 128.
+ *   rho    tile edge: 0 (autotuned), 64, 128 or 256.
  *   deterministic  1: per-tile partial gradients and losses in the
  *          workspace, reduced in a fixed order (bitwise reproducible);
  *          0: atomics (no workspace).
@@ -245,9 +269,12 @@ int tdmap_stress_backward(const float *X, int64_t N, int32_t d, int64_t ldx,
  *              0: autotuned.
  *   workspace  device, tdmap_workspace_size(TDMAP_OP_BATCHED, 0, d, S, rho, 0)
  *              bytes.
- * The offsets are not read on the host (so X_cat and D_cat must be non-NULL
- * whenever num_sets > 0, even if every set is empty); inconsistent offsets
- * are undefined behaviour.  d must be 1..4.  Errors as for tdmap_edm.
+ * The offsets are not read on the host, except that rho = 0 reads
+ * point_off[num_sets] back (one synchronisation of `stream`) to key the
+ * autotuner on the mean set size as well as on num_sets; pass rho to avoid
+ * it.  X_cat and D_cat must be non-NULL whenever num_sets > 0, even if every
+ * set is empty; inconsistent offsets are undefined behaviour.  d must be
+ * 1..4.  Errors as for tdmap_edm.
  */
 int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets,
                       const int64_t *point_off, const int64_t *out_off,
@@ -326,11 +353,14 @@ int tdmap_dummy(int32_t strategy, int32_t variant, int64_t N, int32_t rho, uint3
  * of the call (ignored for TDMAP_OP_BACKWARD, TDMAP_OP_STRESS and
  * TDMAP_OP_BATCHED, except layout 64 for TDMAP_OP_BACKWARD, below); `size`
  * is N for TDMAP_OP_EDM, TDMAP_OP_BACKWARD and
- * TDMAP_OP_STRESS, and num_sets for TDMAP_OP_BATCHED.  Decisions are cached
- * per (op, strategy, layout, d, ceil(log2(size))); for TDMAP_OP_EDM an
+ * TDMAP_OP_STRESS, and num_sets for TDMAP_OP_BATCHED, whose `layout` is
+ * the mean set size in points (point_off[num_sets] / num_sets, rounded
+ * down; the key takes ceil(log2) of it).  Decisions are cached per
+ * (op, strategy, layout, d, ceil(log2(size))); for TDMAP_OP_EDM an
  * output that is not 16-byte aligned (or a full-layout pitch that is not a
- * multiple of 4) is tuned apart, under layout + 64, and for
- * TDMAP_OP_BACKWARD a dD that is not 16-byte aligned under layout 64. */
+ * multiple of 4) is tuned apart, under layout + 64, the Gram precisions
+ * under layout 256 + precision, and for TDMAP_OP_BACKWARD a dD that is not
+ * 16-byte aligned under layout 64. */
 int32_t tdmap_tuned_rho(int32_t op, int32_t strategy, int32_t layout, int32_t d, int64_t size);
 
 /* Forget every autotuner decision. */

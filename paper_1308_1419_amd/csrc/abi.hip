@@ -200,6 +200,39 @@ int validate_edm_common(const float *X, int64_t N, int32_t d, int64_t ldx, const
   return TDMAP_OK;
 }
 
+// Validation and kernel choice of the Gram precisions (rho 0, 128 or 256);
+// with tune, rho = 0 runs the autotuner on the first call of a
+// configuration, otherwise it takes the cached choice or the strips.
+int gram_prepare(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int32_t layout,
+                 int32_t strategy, int32_t rho, int32_t precision, void *workspace,
+                 size_t ws_bytes, void *stream, bool tune, int *ts_out) {
+  const bool split = precision == TDMAP_BF16X3_GRAM;
+  if (strategy != TDMAP_LTM || layout != TDMAP_PACKED || (rho != 0 && rho != 128 && rho != 256))
+    return TDMAP_ERR_UNSUPPORTED;
+  if (N == 0) return TDMAP_OK;
+  if (!tdmap::gram_supported(N, 128) || !tdmap::gram_supported(N, 256))
+    return TDMAP_ERR_UNSUPPORTED;
+  if (workspace == nullptr || ws_bytes < tdmap::gram_workspace_bytes(N, d, split))
+    return TDMAP_ERR_WORKSPACE;
+  int ts = rho;
+  if (ts == 0) {
+    const TuneKey key(TDMAP_OP_EDM, strategy, 256 + precision, d, size_bucket(N));
+    ts = tuned_lookup(key);
+    if (ts == 0 && tune) {
+      hipStream_t s = (hipStream_t)stream;
+      int st = TDMAP_OK;
+      ts = autotune({128, 256}, s,
+                    [&](int c) { return tdmap::launch_gram(X, N, d, ldx, D, workspace, split, c, s); },
+                    &st);
+      if (st != TDMAP_OK) return st;
+      tuned_store(key, ts);
+    }
+    if (ts == 0) ts = 256;
+  }
+  *ts_out = ts;
+  return TDMAP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -224,7 +257,10 @@ void tdmap_autotune_reset(void) {
 
 int32_t tdmap_tuned_rho(int32_t op, int32_t strategy, int32_t layout, int32_t d, int64_t size) {
   if (op != TDMAP_OP_EDM) strategy = 0;
-  if (op != TDMAP_OP_EDM && !(op == TDMAP_OP_BACKWARD && layout == 64)) layout = 0;
+  if (op == TDMAP_OP_BATCHED)
+    layout = size_bucket(layout);  // the mean set size in points
+  else if (op != TDMAP_OP_EDM && !(op == TDMAP_OP_BACKWARD && layout == 64))
+    layout = 0;
   return tuned_lookup(TuneKey(op, strategy, layout, d, size_bucket(size)));
 }
 
@@ -265,9 +301,10 @@ size_t tdmap_workspace_size(int32_t op, int64_t N, int32_t d, int32_t num_sets, 
     case TDMAP_OP_STRESS:
       if (!flags || d > 4) return 0;
       if (rho == 0)
-        return std::max(tdmap::stress_workspace_bytes(N, d, 64),
-                        tdmap::stress_workspace_bytes(N, d, 128));
-      if (rho != 64 && rho != 128) return 0;
+        return std::max({tdmap::stress_workspace_bytes(N, d, 64),
+                         tdmap::stress_workspace_bytes(N, d, 128),
+                         tdmap::stress_workspace_bytes(N, d, 256)});
+      if (rho != 64 && rho != 128 && rho != 256) return 0;
       return tdmap::stress_workspace_bytes(N, d, rho);
     case TDMAP_OP_BATCHED:
       if (num_sets < 0) return 0;
@@ -288,14 +325,12 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int64
   if (!(rho == 0 || rho == 1 || is_cell_rho(rho) || rho == 64 || rho == 128 || rho == 256))
     return TDMAP_ERR_INVALID;
   if (precision != TDMAP_FP32) {
-    const bool split = precision == TDMAP_BF16X3_GRAM;
-    if (strategy != TDMAP_LTM || layout != TDMAP_PACKED || (rho != 0 && rho != 128))
-      return TDMAP_ERR_UNSUPPORTED;
-    if (N == 0) return TDMAP_OK;
-    if (tri(ceil_div((uint64_t)N, 128)) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
-    if (workspace == nullptr || ws_bytes < tdmap::gram_workspace_bytes(N, d, split))
-      return TDMAP_ERR_WORKSPACE;
-    TD_HIP(tdmap::launch_gram(X, N, d, ldx, D, workspace, split, (hipStream_t)stream),
+    int ts = 0;
+    st = gram_prepare(X, N, d, ldx, D, layout, strategy, rho, precision, workspace, ws_bytes,
+                      stream, true, &ts);
+    if (st != TDMAP_OK || N == 0) return st;
+    TD_HIP(tdmap::launch_gram(X, N, d, ldx, D, workspace, precision == TDMAP_BF16X3_GRAM, ts,
+                              (hipStream_t)stream),
            "tdmap_edm");
     return TDMAP_OK;
   }
@@ -345,6 +380,30 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int64
   return TDMAP_OK;
 }
 
+int tdmap_gram_recompute_count(const float *X, int64_t N, int32_t d, int64_t ldx, float *D,
+                               int32_t precision, int32_t rho, void *workspace, size_t ws_bytes,
+                               uint64_t *count, void *stream) {
+  int st = validate_edm_common(X, N, d, ldx, D, 0, TDMAP_PACKED);
+  if (st != TDMAP_OK) return st;
+  if (count == nullptr) return TDMAP_ERR_INVALID;
+  if (precision != TDMAP_BF16_GRAM && precision != TDMAP_BF16X3_GRAM) return TDMAP_ERR_INVALID;
+  if (!(rho == 0 || rho == 128 || rho == 256)) return TDMAP_ERR_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  int ts = 0;
+  st = gram_prepare(X, N, d, ldx, D, TDMAP_PACKED, TDMAP_LTM, rho, precision, workspace, ws_bytes,
+                    stream, false, &ts);
+  if (st != TDMAP_OK) return st;
+  if (N == 0) {
+    TD_HIP(tdmap::launch_fill(reinterpret_cast<float *>(count), 2, 0.0f, s),
+           "tdmap_gram_recompute_count");
+    return TDMAP_OK;
+  }
+  TD_HIP(tdmap::launch_gram_count(X, N, d, ldx, D, workspace, precision == TDMAP_BF16X3_GRAM, ts,
+                                  reinterpret_cast<unsigned long long *>(count), s),
+         "tdmap_gram_recompute_count");
+  return TDMAP_OK;
+}
+
 int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx, const float *dD,
                        int64_t ldd, int32_t layout, float *dX, int32_t rho, int32_t deterministic,
                        void *workspace, size_t ws_bytes, void *stream) {
@@ -390,7 +449,7 @@ int tdmap_stress_backward(const float *X, int64_t N, int32_t d, int64_t ldx, con
   int st = validate_edm_common(X, N, d, ldx, delta, ldd, layout);
   if (st != TDMAP_OK) return st;
   if (loss == nullptr || (N > 0 && dX == nullptr)) return TDMAP_ERR_INVALID;
-  if (rho != 0 && rho != 64 && rho != 128) return TDMAP_ERR_INVALID;
+  if (rho != 0 && rho != 64 && rho != 128 && rho != 256) return TDMAP_ERR_INVALID;
   if (d > 4) return TDMAP_ERR_UNSUPPORTED;
   const uint64_t nb = ceil_div((uint64_t)N, rho ? (uint64_t)rho : 64);
   if (tri(nb) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
@@ -416,7 +475,7 @@ int tdmap_stress_backward(const float *X, int64_t N, int32_t d, int64_t ldx, con
     const TuneKey key(TDMAP_OP_STRESS, 0, 0, d, size_bucket(N));
     ts = tuned_lookup(key);
     if (ts == 0) {
-      ts = autotune({64, 128}, s, run, &st);
+      ts = autotune({64, 128, 256}, s, run, &st);
       if (st != TDMAP_OK) return st;
       tuned_store(key, ts);
     }
@@ -447,7 +506,16 @@ int tdmap_edm_batched(const float *X_cat, int32_t d, int32_t num_sets, const int
   int ts = rho;
   int st = TDMAP_OK;
   if (ts == 0) {
-    const TuneKey key(TDMAP_OP_BATCHED, 0, 0, d, size_bucket(num_sets));
+    // the decision depends on the set sizes as well as their number (the
+    // sweep stages a set in LDS only up to 16384 / d points): key it on the
+    // mean set size too, read back from point_off[num_sets]
+    int64_t total = 0;
+    TD_HIP(hipMemcpyAsync(&total, point_off + num_sets, sizeof(total), hipMemcpyDeviceToHost, s),
+           "tdmap_edm_batched");
+    TD_HIP(hipStreamSynchronize(s), "tdmap_edm_batched");
+    if (total < 0) return TDMAP_ERR_INVALID;
+    const TuneKey key(TDMAP_OP_BATCHED, 0, size_bucket(total / num_sets), d,
+                      size_bucket(num_sets));
     ts = tuned_lookup(key);
     if (ts == 0) {
       ts = autotune({1, 64, 128}, s, run, &st);

@@ -3,17 +3,24 @@
 //   D_ij^2 = ||x_i||^2 + ||x_j||^2 - 2 x_i . x_j
 //
 // A prologue rounds X to BF16 (round to nearest even), pads the features to
-// a multiple of 16 with zeros and the points to a multiple of 128, and
-// computes the squared norms of the rounded points in FP32.  The main
-// kernel walks the triangle by g(lambda) (Sec. II-A, Eq. (2)) on 256 x 256
-// tiles, a work-group taking one row half (two 128 x 128 tiles side by
-// side); each wave owns 32 rows x 128 columns of one of them, computed by
-// four v_mfma_f32_32x32x16_bf16 accumulators (BF16 products are exact in
-// FP32, the sums accumulate in FP32).  The epilogue forms
-// G = n_i + n_j - 2 acc and, when G <= theta (n_i + n_j) (theta = 1/4:
-// the pair is close relative to its norms, where the Gram form cancels),
-// recomputes the distance exactly in FP32 difference form from the FP32
-// points; otherwise it stores sqrt(G).
+// a multiple of 16 with zeros and the points to a multiple of 256, and
+// computes the squared norms of the rounded points in FP32.  The products
+// are taken by v_mfma_f32_32x32x16_bf16 on 32 x 32 output blocks (BF16
+// products are exact in FP32, the sums accumulate in FP32).  The epilogue
+// forms G = n_i + n_j - 2 acc and, when G <= theta (n_i + n_j) (theta =
+// 1/4: the pair is close relative to its norms, where the Gram form
+// cancels), recomputes the distance exactly in FP32 difference form from the
+// FP32 points; otherwise it stores sqrt(G).
+//
+// Two kernels walk the triangle by g(lambda) (Sec. II-A, Eq. (2)) and
+// compute every 32 x 32 block with the same instructions in the same order,
+// so their outputs are equal bit for bit:
+//   - gram_tile_kernel: a work-group of eight waves owns one row half (two
+//     128 x 128 tiles side by side) of a 256 x 256 tile;
+//   - gram_strip_kernel: a work-group of four waves owns a 32-row strip of
+//     a 256 x 256 tile, the strips of a tile row taken strip by strip across
+//     the row (the order of the FP32 strips), so that the writes in flight
+//     stay in a compact window of the packed output.
 //
 // Split mode (precision BF16X3): each point is held as x = hi + lo with
 // hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in FP32, and hi + lo
@@ -27,8 +34,10 @@ namespace tdmap {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGramTile = 128;
+constexpr int kGramTile = 128;  // tile kernel: 128 x 128 per eight waves
+constexpr int kGramPad = 256;   // operand rows are padded to this
 constexpr float kGramTheta = 0.25f;
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
@@ -88,50 +97,105 @@ __device__ __forceinline__ float exact_dist(const float *__restrict__ X, int64_t
   return __builtin_amdgcn_sqrtf(q);
 }
 
-typedef float f4 __attribute__((ext_vector_type(4)));
+// The products of NB 32 x 32 blocks sharing one 32-row block of A: block b
+// takes the 32 points starting at col[b].  Lane l supplies row (l % 32) of
+// a 32-row block and the 8 features [8 (l / 32), 8 (l / 32) + 8) of each
+// 16-feature step; B uses the same assignment for its points, so the
+// product is x_i . x_j.  Blocks with live[b] false are left at zero.  The
+// steps run in increasing feature order and, in split mode, each step adds
+// lo.hi', hi.lo', hi.hi' in that order: every kernel that calls this gets
+// the same bits for the same block.
+template <bool SPLIT, int KPC, int NB>
+__device__ __forceinline__ void gram_products(const GramArgs &a, int KP, int64_t row, const int64_t (&col)[NB],
+                                              const bool (&live)[NB], f32x16 (&acc)[NB]) {
+  const int l = threadIdx.x & 63;
+  const int lr = l & 31;
+  const int lk = (l >> 5) * 8;
+  const uint16_t *__restrict__ Xb = a.Xb;
+  const uint16_t *__restrict__ Xl = a.Xlo;
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[b][v] = 0.0f;
+  auto kstep = [&](int k) {
+    const int64_t ao = (row + lr) * KP + k + lk;
+    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Xb + ao);
+    bf16x8 al;
+    if constexpr (SPLIT) al = *reinterpret_cast<const bf16x8 *>(Xl + ao);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (live[b]) {
+        const int64_t bo = (col[b] + lr) * KP + k + lk;
+        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Xb + bo);
+        if constexpr (SPLIT) {
+          const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(Xl + bo);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bv, acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bl, acc[b], 0, 0, 0);
+        }
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[b], 0, 0, 0);
+      }
+    }
+  };
+  if constexpr (KPC != 0) {
+#pragma unroll
+    for (int k = 0; k < KPC; k += 16) kstep(k);
+  } else {
+    for (int k = 0; k < KP; k += 16) kstep(k);
+  }
+}
 
-// Each wave owns 32 whole rows of the 128 x 128 tile: four 32 x 32
-// v_mfma_f32_32x32x16_bf16 accumulators (one per 32-column block).  Its
-// distances go, 16 rows at a time, through a wave-private LDS slice and are
-// written as packed rows with 16-byte stores; no work-group barrier is
-// needed, so the waves run independently.
-//
-// Store layout: a half-wave writes one 128-cell row segment.  Packed row i's
-// segment [col0, col0 + 128) starts sh = (i(i+1)/2 + col0) mod 4 positions
-// past a 16-byte boundary; lane h stores the aligned chunk at columns
-// col0 - sh + 4h .. + 3, read from LDS at that shift.  The cells of the two
-// partial chunks at the ends of each segment (the neighbouring tiles write
-// the rest of those chunks) are gathered one row per lane and written with
-// four instructions per 16 rows: single-lane stores per row would multiply
-// the store instruction count several times over.  Diagonal and edge rows
-// go cell by cell.
-constexpr int kGramRows = 16;  // rows staged per step and wave
+// Accumulator v of a 32 x 32 block holds row (v/4)*8 + (l/32)*4 + v%4 of
+// the block and column l % 32.
+__device__ __forceinline__ int acc_row(int v, int l) { return (v >> 2) * 8 + (l >> 5) * 4 + (v & 3); }
 
-// (i(i+1)/2 + col0) mod 4 for the tile row rr of a 16-row step: the step's
-// first row is a multiple of 16 and col0 a multiple of 128, and
-// i(i+1)/2 mod 4 has period 8 in i.
+// The epilogue value of one pair from its accumulator and the two squared
+// norms: sqrt(G), or -1 for a pair below the threshold (filled in by the
+// exact recompute).
+__device__ __forceinline__ float gram_value(float acc, float ni, float nj) {
+  const float sn = ni + nj;
+  const float G = __builtin_fmaf(-2.0f, acc, sn);
+  return G <= kGramTheta * sn ? -1.0f : __builtin_amdgcn_sqrtf(G);
+}
+
+// (i(i+1)/2 + c) mod 4 for a row i that is a multiple of 32 plus rr and a
+// column c that is a multiple of 128: i(i+1)/2 mod 4 has period 8 in i.
 __device__ __forceinline__ int row_shift(int rr) {
   const int m = rr & 7;
   return ((m * (m + 1)) >> 1) & 3;
 }
 
+// ---------------------------------------------------------------------------
+// tile kernel: eight waves, two 128 x 128 tiles side by side
+// ---------------------------------------------------------------------------
 
-// KPC: the padded feature count as a compile-time constant (16, 32, 64 or
-// 128), which unrolls the MFMA loop so that the loads of every feature step
-// are issued before the first product waits (measured: split form 9.5 ->
-// 8.7 ms at N = 100000, d = 64); 0 for any other count.
-template <bool SPLIT, int KPC>
+// Each wave owns 32 whole rows of the 128 x 128 tile: four 32 x 32
+// accumulators (one per 32-column block).  Its distances go, 16 rows at a
+// time, through a wave-private LDS slice and are written as packed rows with
+// 16-byte stores; no work-group barrier is needed, so the waves run
+// independently.
+//
+// Store layout: a half-wave writes one 128-cell row segment.  Packed row i's
+// segment [col0, col0 + 128) starts sh = (D / 4 + i(i+1)/2 + col0) mod 4
+// positions past a 16-byte boundary (D / 4: the output's own offset in
+// floats); lane h stores the aligned chunk at columns col0 - sh + 4h .. + 3,
+// read from LDS at that shift.  The cells of the two partial chunks at the
+// ends of each segment (the neighbouring tiles write the rest of those
+// chunks) are gathered one row per lane and written with four instructions
+// per 16 rows: single-lane stores per row would multiply the store
+// instruction count several times over.  Diagonal and edge rows go cell by
+// cell.
+constexpr int kGramRows = 16;  // rows staged per step and wave
+
+template <bool SPLIT, int KPC, bool COUNT>
 __global__ __launch_bounds__(512, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs a, uint32_t lam0,
                                                                       uint32_t nblk) {
   // Eight waves: the two side-by-side 128 x 128 tiles (I, 2 J2) and
   // (I, 2 J2 + 1) that form one row half, I = 2 I2 + wg mod 2, of the
   // 256 x 256 tile (I2, J2) = g(wg / 2), so each row is written as a 1 KB
-  // segment (measured 7.2 -> 7.0 ms, split 8.7 -> 8.4 ms, against one 128 x
-  // 128 tile per work-group; four tiles side by side gave the gain back).
-  // Each XCD takes one contiguous range of wg: neighbouring tiles share
-  // the partial 16-byte chunks (and lines) at the ends of their row
-  // segments, which then combine in one L2 (measured 9.6 -> 7.2 ms), and
-  // they share their BF16 row block.
+  // segment.  Each XCD takes one contiguous range of wg: neighbouring tiles
+  // share the partial 16-byte chunks (and lines) at the ends of their row
+  // segments, which then combine in one L2, and they share their BF16 row
+  // block.
   const uint32_t wg = lam0 + xcd_contiguous(blockIdx.x, nblk);
   uint32_t I2, J2;
   g_lambda(wg >> 1, I2, J2);
@@ -145,84 +209,54 @@ __global__ __launch_bounds__(512, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
   const int w = wl & 3;  // the wave's 32-row block of its 128 x 128 tile
   const int l = threadIdx.x & 63;
   const int lr = l & 31;
-  const int lk = (l >> 5) * 8;
   const int64_t N = a.N;
   const int64_t row0 = (int64_t)I * kGramTile;
   const int64_t col0 = (int64_t)J * kGramTile;
   const int64_t rw = row0 + 32 * w;  // this wave's first row
   const bool diag = I == J;
-  // on a diagonal tile, column blocks right of this wave's rows are above
-  // the diagonal
-  const int nbj = diag ? w + 1 : 4;
   const int KP = KPC ? KPC : a.KP;
-  const uint16_t *__restrict__ Xb = a.Xb;
+  const int bsh = (int)((reinterpret_cast<uintptr_t>(a.D) >> 2) & 3);
+  auto shift = [&](int rr) { return (row_shift(rr) + bsh) & 3; };
 
   float nr[16];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) nr[v] = a.nrm[rw + (v >> 2) * 8 + (l >> 5) * 4 + (v & 3)];
+  for (int v = 0; v < 16; ++v) nr[v] = a.nrm[rw + acc_row(v, l)];
   float nc[4];
 #pragma unroll
   for (int bj = 0; bj < 4; ++bj) nc[bj] = a.nrm[col0 + bj * 32 + lr];
 
-  f32x16 acc[4];
+  // on a diagonal tile, column blocks right of this wave's rows are above
+  // the diagonal
+  int64_t cols[4];
+  bool live[4];
 #pragma unroll
-  for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[bj][v] = 0.0f;
-  // lane l supplies row (l % 32) of a 32-row block and the 8 features
-  // [8 (l / 32), 8 (l / 32) + 8) of each 16-feature step; B uses the same
-  // assignment for its points, so the product is x_i . x_j.
-  const uint16_t *__restrict__ Xl = a.Xlo;
-  auto kstep = [&](int k) {
-    const int64_t ao = (rw + lr) * KP + k + lk;
-    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Xb + ao);
-    bf16x8 al;
-    if constexpr (SPLIT) al = *reinterpret_cast<const bf16x8 *>(Xl + ao);
-#pragma unroll
-    for (int bj = 0; bj < 4; ++bj) {
-      if (bj < nbj) {
-        const int64_t bo = (col0 + bj * 32 + lr) * KP + k + lk;
-        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Xb + bo);
-        if constexpr (SPLIT) {
-          const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(Xl + bo);
-          acc[bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bv, acc[bj], 0, 0, 0);
-          acc[bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bl, acc[bj], 0, 0, 0);
-        }
-        acc[bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[bj], 0, 0, 0);
-      }
-    }
-  };
-  if constexpr (KPC != 0) {
-#pragma unroll
-    for (int k = 0; k < KPC; k += 16) kstep(k);
-  } else {
-    for (int k = 0; k < KP; k += 16) kstep(k);
+  for (int bj = 0; bj < 4; ++bj) {
+    cols[bj] = col0 + bj * 32;
+    live[bj] = !diag || bj <= w;
   }
+  f32x16 acc[4];
+  gram_products<SPLIT, KPC, 4>(a, KP, rw, cols, live, acc);
 
-  // stage row rr holds column c at position c + sh(rr), where sh(rr) is the
-  // offset of the packed row past a 16-byte boundary; the stored chunks are
-  // then aligned 16-byte LDS reads without bank conflicts
+  // stage row rr holds column c at position c + shift(rr); the stored
+  // chunks are then aligned 16-byte LDS reads without bank conflicts
   __shared__ __align__(16) float stage[8][kGramRows][kGramTile + 4];
   float(*st)[kGramTile + 4] = stage[wl];
   float *__restrict__ out = a.D;
   const int h = l & 31;
   const bool full_rows = !diag && row0 + kGramTile <= N;
+  uint32_t nrec = 0;
 #pragma unroll
   for (int vh = 0; vh < 2; ++vh) {
-    // accumulator v of a 32 x 32 block holds row (v/4)*8 + (l/32)*4 + v%4
-    // and column l % 32; v in [8 vh, 8 vh + 8) are the rows 16 vh .. +15
+    // v in [8 vh, 8 vh + 8) are the rows 16 vh .. +15
     bool any = false;
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) {
 #pragma unroll
       for (int v = 8 * vh; v < 8 * vh + 8; ++v) {
-        const int rr = (v >> 2) * 8 + (l >> 5) * 4 + (v & 3) - 16 * vh;
-        const float sn = nr[v] + nc[bj];
-        const float G = __builtin_fmaf(-2.0f, acc[bj][v], sn);
-        const bool rec = G <= kGramTheta * sn;
-        any |= rec;
-        // a pair below the threshold is marked -1 and filled in below
-        st[rr][bj * 32 + lr + row_shift(rr)] = rec ? -1.0f : __builtin_amdgcn_sqrtf(G);
+        const int rr = acc_row(v, l) - 16 * vh;
+        const float g = gram_value(acc[bj][v], nr[v], nc[bj]);
+        any |= g < 0.0f;
+        st[rr][bj * 32 + lr + shift(rr)] = g;
       }
     }
     if (any) {
@@ -231,12 +265,14 @@ __global__ __launch_bounds__(512, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
       for (int bj = 0; bj < 4; ++bj) {
 #pragma unroll
         for (int v = 8 * vh; v < 8 * vh + 8; ++v) {
-          const int rr = (v >> 2) * 8 + (l >> 5) * 4 + (v & 3) - 16 * vh;
-          const int c = bj * 32 + lr + row_shift(rr);
+          const int rr = acc_row(v, l) - 16 * vh;
+          const int c = bj * 32 + lr + shift(rr);
           if (st[rr][c] < 0.0f) {
             const int64_t i = rw + 16 * vh + rr;
             const int64_t j = col0 + bj * 32 + lr;
-            st[rr][c] = (i < N && j <= i) ? exact_dist(a.X, a.ldx, a.d, i, j) : 0.0f;
+            const bool cell = i < N && j <= i;
+            if (COUNT) nrec += cell;
+            st[rr][c] = cell ? exact_dist(a.X, a.ldx, a.d, i, j) : 0.0f;
           }
         }
       }
@@ -245,8 +281,8 @@ __global__ __launch_bounds__(512, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
     if (full_rows) {
       // Row rw + m (m < 32) starts at T(rw) + col0 + m rw + m(m+1)/2: a
       // uniform base and a 32-bit offset (m rw < 32 N < 2^30 under the
-      // 32-bit tile index), with the row's shift row_shift(m) (rw is a
-      // multiple of 32, so T(rw) and m rw add nothing mod 4).
+      // 32-bit tile index), with the row's shift shift(m) (rw is a multiple
+      // of 32, so T(rw) and m rw add nothing mod 4).
       float *__restrict__ outw = out + tri64((uint64_t)rw) + (uint64_t)col0;
       const uint32_t rw32 = (uint32_t)rw;
       auto row_off = [&](uint32_t m) { return m * rw32 + ((m * (m + 1)) >> 1); };
@@ -259,7 +295,7 @@ __global__ __launch_bounds__(512, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
       for (int p = 0; p < kGramRows / 2; ++p) {
         const int r = 2 * p + (l >> 5);
         const uint32_t m = 16 * vh + r;
-        const int sh = row_shift(r);
+        const int sh = shift(r);
         if (h > 0 || sh == 0) {
           const f4 v4 = *reinterpret_cast<const f4 *>(&st[r][4 * h]);
           f4 *dst = reinterpret_cast<f4 *>(at(row_off(m) - sh + 4 * h));
@@ -277,7 +313,7 @@ __global__ __launch_bounds__(512, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
       // one row per lane, four instructions for all 16 rows
       if (l < kGramRows) {
         const uint32_t m = 16 * vh + l;
-        const int sh = row_shift(l);
+        const int sh = shift(l);
         if (sh != 0) {
           const uint32_t o0 = row_off(m);
 #pragma unroll
@@ -296,46 +332,255 @@ __global__ __launch_bounds__(512, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
         const int64_t i = rw + 16 * vh + r;
         if (i >= N) continue;
         const uint64_t first = tri64((uint64_t)i) + (uint64_t)col0;
-        const int sh = (int)(first & 3);
+        const int sh = shift(r);
         const int64_t jmax = (diag ? i : N - 1) - col0;
         for (int c = h; c < kGramTile; c += 32)
           if (c <= jmax) __builtin_nontemporal_store(st[r][c + sh], out + first + c);
       }
     }
   }
+  if (COUNT && nrec) atomicAdd(a.rec_count, (unsigned long long)nrec);
 }
 
-template <bool SPLIT>
+// ---------------------------------------------------------------------------
+// strip kernel: four waves, one 32-row strip of a 256 x 256 tile
+// ---------------------------------------------------------------------------
+
+// Tile row I (256 rows) is cut into kStripsPerTile strips of 32 rows and a
+// work-group computes one strip of one tile, 32 x 256 cells; wave q owns the
+// columns [64 q, 64 q + 64) (two 32 x 32 accumulators).  The strips of tile
+// row I are numbered u = 0 .. 8 (I + 1) - 1 and taken in column groups of
+// `group` tiles: group outer, strip next, tile column inner.  With one group
+// per tile row the work-groups in flight write a few whole 32-row bands of
+// the packed triangle (one compact window of addresses per XCD, as in the
+// FP32 strips); a narrower group keeps the group's BF16 column points in L2
+// across its strips.  The distances go through LDS (one work-group barrier)
+// and leave as whole packed rows: wave q writes rows q, q + 4, ..., each
+// with four 4-byte store instructions of 256 contiguous bytes (lane l owns
+// columns l + 64 c), or (kStripStore16) one 16-byte store instruction of
+// the aligned chunks plus the partial chunks at both ends, gathered over the
+// wave's rows.
+constexpr int kStripRows = 32;
+constexpr int kStripsPerTile = 256 / kStripRows;
+constexpr int kStripPitch = 264;  // LDS row pitch: rows r and r + 4 land 32 banks apart
+// column group (tiles) and store form of the strip kernel
+constexpr uint32_t kStripGroup = 0xffffffffu;
+constexpr bool kStripStore16 = false;
+
+template <bool SPLIT, int KPC, bool COUNT>
+__global__ __launch_bounds__(256) void gram_strip_kernel(GramArgs a, uint32_t w0, uint32_t nblk,
+                                                         uint32_t group) {
+  const uint32_t w = w0 + xcd_contiguous(blockIdx.x, nblk);
+  uint32_t I, Jt;
+  g_lambda(w / kStripsPerTile, I, Jt);
+  // u: this work-group's place among the 8 (I + 1) strips of tile row I
+  const uint32_t u = kStripsPerTile * Jt + w % kStripsPerTile;
+  const uint32_t ntile = I + 1;
+  const uint32_t gs = group < ntile ? group : ntile;
+  const uint32_t nfull = ntile / gs;
+  const uint32_t span = gs * kStripsPerTile;
+  uint32_t k, J;
+  if (u < nfull * span) {
+    const uint32_t g = u / span, r = u - g * span;
+    k = r / gs;
+    J = g * gs + (r - k * gs);
+  } else {
+    const uint32_t rem = ntile - nfull * gs;  // the last, narrower group
+    const uint32_t r = u - nfull * span;
+    k = r / rem;
+    J = nfull * gs + (r - k * rem);
+  }
+  const int64_t N = a.N;
+  const int64_t r0 = (int64_t)I * 256 + (int64_t)k * kStripRows;
+  if (r0 >= N) return;  // a strip past the last point (uniform)
+  const int64_t c0 = (int64_t)J * 256;
+  const bool diag = I == J;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  const int lr = l & 31;
+  const int KP = KPC ? KPC : a.KP;
+  const int bsh = (int)((reinterpret_cast<uintptr_t>(a.D) >> 2) & 3);
+  // LDS position of column c of strip row r: shifted so that the 16-byte
+  // store chunks are aligned LDS reads (16-byte form only)
+  auto shift = [&](int r) { return kStripStore16 ? (row_shift(r) + bsh) & 3 : 0; };
+
+  float nr[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) nr[v] = a.nrm[r0 + acc_row(v, l)];
+  int64_t cols[2];
+  bool live[2];
+  float nc[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int cb = 64 * q + 32 * b;  // block column within the tile
+    cols[b] = c0 + cb;
+    nc[b] = a.nrm[c0 + cb + lr];
+    // on a diagonal tile, blocks right of the strip's last row are above
+    // the diagonal
+    live[b] = !diag || cb < kStripRows * ((int)k + 1);
+  }
+  f32x16 acc[2];
+  gram_products<SPLIT, KPC, 2>(a, KP, r0, cols, live, acc);
+
+  __shared__ __align__(16) float st[kStripRows][kStripPitch];
+  bool any = false;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int rr = acc_row(v, l);
+      const float g = gram_value(acc[b][v], nr[v], nc[b]);
+      any |= g < 0.0f;
+      st[rr][64 * q + 32 * b + lr + shift(rr)] = g;
+    }
+  }
+  uint32_t nrec = 0;
+  if (any) {
+    // rare: the diagonal and near-duplicate pairs, exact FP32 difference
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int rr = acc_row(v, l);
+        const int c = 64 * q + 32 * b + lr;
+        if (st[rr][c + shift(rr)] < 0.0f) {
+          const int64_t i = r0 + rr;
+          const int64_t j = c0 + c;
+          const bool cell = i < N && j <= i;
+          if (COUNT) nrec += cell;
+          st[rr][c + shift(rr)] = cell ? exact_dist(a.X, a.ldx, a.d, i, j) : 0.0f;
+        }
+      }
+    }
+  }
+  if (COUNT && nrec) atomicAdd(a.rec_count, (unsigned long long)nrec);
+  __syncthreads();
+
+  // Strip row r starts at T(r0 + r) + c0 = T(r0) + c0 + r r0 + r(r+1)/2: a
+  // uniform 64-bit base and a 32-bit offset (r r0 < 32 N).
+  float *__restrict__ outb = a.D + tri64((uint64_t)r0) + (uint64_t)c0;
+  const uint32_t r0u = (uint32_t)r0;
+  auto row_off = [&](uint32_t r) { return r * r0u + ((r * (r + 1)) >> 1); };
+  const bool interior = !diag && r0 + kStripRows <= N;
+  if (interior && kStripStore16) {
+#pragma unroll
+    for (int m = 0; m < kStripRows / 4; ++m) {
+      const int r = q + 4 * m;
+      const int sh = shift(r);
+      if (l > 0 || sh == 0) {
+        const f4 v4 = *reinterpret_cast<const f4 *>(&st[r][4 * l]);
+        *reinterpret_cast<f4 *>(outb + row_off(r) - sh + 4 * l) = v4;
+      }
+    }
+    // the 4 - sh head cells and sh tail cells of the wave's 8 rows, one
+    // cell per lane
+    if (l < 32) {
+      const int r = q + 4 * (l >> 2);
+      const int c4 = l & 3;
+      const int sh = shift(r);
+      if (sh != 0) {
+        const int c = c4 < 4 - sh ? c4 : 252 + c4;
+        outb[row_off(r) + c] = st[r][c + sh];
+      }
+    }
+  } else if (interior) {
+#pragma unroll
+    for (int m = 0; m < kStripRows / 4; ++m) {
+      const int r = q + 4 * m;
+      float *o = outb + row_off(r);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) o[l + 64 * c] = st[r][l + 64 * c];
+    }
+  } else {
+    // diagonal or edge strip: rows below N, cells with j <= i
+    for (int m = 0; m < kStripRows / 4; ++m) {
+      const int r = q + 4 * m;
+      const int64_t i = r0 + r;
+      if (i >= N) break;
+      const int64_t jmax = diag ? i - c0 : 255;
+      float *o = outb + row_off(r);
+      const int sh = shift(r);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int col = l + 64 * c;
+        if (col <= jmax) o[col] = st[r][col + sh];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+template <bool SPLIT, bool COUNT>
 static void launch_gram_tiles(int KP, dim3 grid, hipStream_t stream, const GramArgs &a, uint32_t l0) {
   const dim3 block(512);
   switch (KP) {
     case 16:
-      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 16>), grid, block, 0, stream, a, l0, grid.x);
+      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 16, COUNT>), grid, block, 0, stream, a, l0, grid.x);
       break;
     case 32:
-      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 32>), grid, block, 0, stream, a, l0, grid.x);
+      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 32, COUNT>), grid, block, 0, stream, a, l0, grid.x);
       break;
     case 64:
-      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 64>), grid, block, 0, stream, a, l0, grid.x);
+      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 64, COUNT>), grid, block, 0, stream, a, l0, grid.x);
       break;
     case 128:
-      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 128>), grid, block, 0, stream, a, l0, grid.x);
+      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 128, COUNT>), grid, block, 0, stream, a, l0, grid.x);
       break;
     default:
-      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 0>), grid, block, 0, stream, a, l0, grid.x);
+      hipLaunchKernelGGL((gram_tile_kernel<SPLIT, 0, COUNT>), grid, block, 0, stream, a, l0, grid.x);
   }
 }
 
+template <bool SPLIT, bool COUNT>
+static void launch_gram_strips(int KP, dim3 grid, hipStream_t stream, const GramArgs &a, uint32_t w0) {
+  const dim3 block(256);
+  const uint32_t g = kStripGroup;
+  switch (KP) {
+    case 16:
+      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 16, COUNT>), grid, block, 0, stream, a, w0, grid.x, g);
+      break;
+    case 32:
+      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 32, COUNT>), grid, block, 0, stream, a, w0, grid.x, g);
+      break;
+    case 64:
+      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 64, COUNT>), grid, block, 0, stream, a, w0, grid.x, g);
+      break;
+    case 128:
+      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 128, COUNT>), grid, block, 0, stream, a, w0, grid.x, g);
+      break;
+    default:
+      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 0, COUNT>), grid, block, 0, stream, a, w0, grid.x, g);
+  }
+}
+
+static int64_t gram_npad(int64_t N) { return (N + kGramPad - 1) / kGramPad * kGramPad; }
+
 size_t gram_workspace_bytes(int64_t N, int d, bool split) {
-  const int64_t Npad = (N + kGramTile - 1) / kGramTile * kGramTile;
   const int64_t KP = (d + 15) / 16 * 16;
+  const int64_t Npad = gram_npad(N);
   return (size_t)Npad * (size_t)KP * 2 * (split ? 2 : 1) + (size_t)Npad * 4;
 }
 
-hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws, bool split,
-                       hipStream_t stream) {
+bool gram_supported(int64_t N, int ts) {
+  if (ts == 128) {
+    const uint64_t nb2 = (uint64_t)((N + 255) / 256);
+    return nb2 * (nb2 + 1) <= 0xffffffffull;
+  }
+  if (ts == 256) {
+    const uint64_t nb = (uint64_t)((N + 255) / 256);
+    return (uint64_t)kStripsPerTile * (nb * (nb + 1) / 2) <= 0xffffffffull;
+  }
+  return false;
+}
+
+template <bool COUNT>
+static hipError_t launch_gram_t(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws,
+                                bool split, int ts, unsigned long long *count, hipStream_t stream) {
   if (N == 0) return hipSuccess;
-  const int64_t Npad = (N + kGramTile - 1) / kGramTile * kGramTile;
+  const int64_t Npad = gram_npad(N);
   const int KP = (d + 15) / 16 * 16;
   // workspace: hi parts, [lo parts,] norms
   uint16_t *Xb = reinterpret_cast<uint16_t *>(ws);
@@ -346,20 +591,46 @@ hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, 
                      X, N, d, ldx, Xb, Xlo, nrm, Npad, KP);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  GramArgs a{X, N, d, ldx, Xb, Xlo, nrm, KP, D};
-  const uint64_t nb = (uint64_t)(Npad / kGramTile);
-  const uint64_t nb2 = (nb + 1) / 2;
+  GramArgs a{X, N, d, ldx, Xb, Xlo, nrm, KP, D, count};
+  if (ts == 256) {
+    const uint64_t nb = (uint64_t)(Npad / 256);
+    const uint64_t W = (uint64_t)kStripsPerTile * (nb * (nb + 1) / 2);
+    const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
+    for (uint64_t w0 = 0; w0 < W; w0 += max_blocks) {
+      const uint64_t c = W - w0 < max_blocks ? W - w0 : max_blocks;
+      if (split)
+        launch_gram_strips<true, COUNT>(KP, dim3((uint32_t)c), stream, a, (uint32_t)w0);
+      else
+        launch_gram_strips<false, COUNT>(KP, dim3((uint32_t)c), stream, a, (uint32_t)w0);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  if (ts != 128) return hipErrorInvalidValue;
+  const uint64_t nb2 = (uint64_t)(Npad / 256);
   const uint64_t T = nb2 * (nb2 + 1);  // two work-groups per 256 x 256 tile
   const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 512;
   for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
     const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
     if (split)
-      launch_gram_tiles<true>(KP, dim3((uint32_t)c), stream, a, (uint32_t)l0);
+      launch_gram_tiles<true, COUNT>(KP, dim3((uint32_t)c), stream, a, (uint32_t)l0);
     else
-      launch_gram_tiles<false>(KP, dim3((uint32_t)c), stream, a, (uint32_t)l0);
+      launch_gram_tiles<false, COUNT>(KP, dim3((uint32_t)c), stream, a, (uint32_t)l0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws, bool split,
+                       int ts, hipStream_t stream) {
+  return launch_gram_t<false>(X, N, d, ldx, D, ws, split, ts, nullptr, stream);
+}
+
+hipError_t launch_gram_count(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws,
+                             bool split, int ts, unsigned long long *count, hipStream_t stream) {
+  hipError_t e = launch_fill(reinterpret_cast<float *>(count), 2, 0.0f, stream);
+  if (e != hipSuccess) return e;
+  return launch_gram_t<true>(X, N, d, ldx, D, ws, split, ts, count, stream);
 }
 
 }  // namespace tdmap

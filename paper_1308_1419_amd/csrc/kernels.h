@@ -88,18 +88,25 @@ struct GramArgs {
   int64_t N;
   int d;
   int64_t ldx;
-  const uint16_t *Xb;  // BF16 points, padded: ceil(N/128)*128 rows of KP features
+  const uint16_t *Xb;  // BF16 points, padded: ceil(N/256)*256 rows of KP features
   const uint16_t *Xlo; // split mode: BF16 low parts x - hi, same layout; else nullptr
   const float *nrm;    // squared norms of the represented points
   int KP;              // features padded to a multiple of 16
   float *D;            // packed output
+  unsigned long long *rec_count;  // instrumented launches: recomputed pairs
 };
 
 // BF16 Gram-form EDM (packed), workspace of gram_workspace_bytes(N, d,
-// split); split = the hi + lo representation with three products.
+// split); split = the hi + lo representation with three products.  ts
+// selects the kernel: 128 the eight-wave tiles, 256 the 32-row strips.
 size_t gram_workspace_bytes(int64_t N, int d, bool split);
+bool gram_supported(int64_t N, int ts);
 hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws, bool split,
-                       hipStream_t stream);
+                       int ts, hipStream_t stream);
+// The same launch with every recomputed pair (i, j), j <= i < N, counted
+// into *count (zeroed first).
+hipError_t launch_gram_count(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws,
+                             bool split, int ts, unsigned long long *count, hipStream_t stream);
 
 // Packed layout written as a linear sweep (g at one-cell granularity).
 bool sweep_supported(const EdmArgs &a);

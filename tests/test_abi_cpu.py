@@ -126,15 +126,15 @@ def test_stress_validation_and_workspace(lib):
     L = tdmap._load()
     N, d = 1000, 3
     # per tile: 2 ts d gradient partials and one loss partial
-    for ts in (64, 128):
+    for ts in (64, 128, 256):
         nb = -(-N // ts)
         T = nb * (nb + 1) // 2
         assert tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, ts, 1) == \
             T * (2 * ts * d + 1) * 4
     assert tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, 0, 1) == max(
-        tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, ts, 1) for ts in (64, 128))
+        tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, ts, 1) for ts in (64, 128, 256))
     assert tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, 64, 0) == 0
-    assert tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, 256, 1) == 0
+    assert tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, 512, 1) == 0
     assert tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, 5, 0, 64, 1) == 0
     P = tdmap.PACKED
     # NULL loss / dX / delta, bad rho, d > 4, a workspace too small
@@ -144,7 +144,7 @@ def test_stress_validation_and_workspace(lib):
         == tdmap.ERR_INVALID
     assert L.tdmap_stress_backward(8, N, d, d, None, 0, P, 8, 8, 64, 0, None, 0, None) \
         == tdmap.ERR_INVALID
-    assert L.tdmap_stress_backward(8, N, d, d, 16, 0, P, 8, 8, 256, 0, None, 0, None) \
+    assert L.tdmap_stress_backward(8, N, d, d, 16, 0, P, 8, 8, 512, 0, None, 0, None) \
         == tdmap.ERR_INVALID
     assert L.tdmap_stress_backward(8, N, 5, 5, 16, 0, P, 8, 8, 64, 0, None, 0, None) \
         == tdmap.ERR_UNSUPPORTED
@@ -200,3 +200,17 @@ def test_product_path_never_imports_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert not pat.search(text), f
+
+
+def test_gram_kernel_choice_validates(lib):
+    L = tdmap._load()
+    G = tdmap.BF16_GRAM
+    # Gram: rho 0, 128 or 256 only; packed LTM only
+    assert L.tdmap_edm(8, 10, 64, 64, 8, 0, tdmap.PACKED, 0, 64, G, 8, 1 << 20, None) \
+        == tdmap.ERR_UNSUPPORTED
+    assert L.tdmap_edm(8, 10, 64, 64, 8, 0, tdmap.PACKED, 0, 256, G, None, 0, None) \
+        == tdmap.ERR_WORKSPACE
+    assert L.tdmap_gram_recompute_count(8, 10, 64, 64, 8, G, 256, 8, 1 << 20, None, None) \
+        == tdmap.ERR_INVALID
+    assert L.tdmap_gram_recompute_count(8, 10, 64, 64, 8, tdmap.FP32, 256, 8, 1 << 20, 8,
+                                        None) == tdmap.ERR_INVALID
