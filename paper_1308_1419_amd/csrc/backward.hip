@@ -513,6 +513,10 @@ __global__ __launch_bounds__(TS * D * bwd_reduce_groups<TS * D>()) void edm_bwd_
   }
 }
 
+// The backward at TS = 256: the 16-byte load kernel above (true), or the
+// 16-lane row-group tile of edm_bwd_tile with eight columns per lane (false).
+constexpr bool kBwd256Vector = true;
+
 template <int TS, int D, int LAYOUT, bool DET>
 static hipError_t launch_bwd_t(const BwdArgs &a) {
   const uint64_t nb = (uint64_t)((a.N + TS - 1) / TS);
@@ -524,7 +528,7 @@ static hipError_t launch_bwd_t(const BwdArgs &a) {
   const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
   for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
     const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
-    if constexpr (TS == 256) {
+    if constexpr (TS == 256 && kBwd256Vector) {
       hipLaunchKernelGGL((edm_bwd_tile256<D, LAYOUT, DET>), dim3((uint32_t)c), dim3(256), 0,
                          a.stream, a, (uint32_t)l0);
     } else {
@@ -624,6 +628,7 @@ hipError_t launch_stress(int ts, const BwdArgs &a) {
   switch (ts) {
     case 64: return launch_stress_ts<64>(a);
     case 128: return launch_stress_ts<128>(a);
+    case 256: return launch_stress_ts<256>(a);
     default: return hipErrorInvalidValue;
   }
 }

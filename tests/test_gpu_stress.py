@@ -30,6 +30,7 @@ pytestmark = pytest.mark.gpu
 from paper_1308_1419_amd import tdmap  # noqa: E402
 
 U = 2.0 ** -24
+TILES = (64, 128, 256)
 
 
 def _require_gpu():
@@ -94,7 +95,7 @@ def _device_targets(delta, N, layout):
 
 
 @pytest.mark.parametrize("layout", ["packed", "strict", "full"])
-@pytest.mark.parametrize("rho", [64, 128, 0])
+@pytest.mark.parametrize("rho", [64, 128, 256, 0])
 @pytest.mark.parametrize("det", [True, False])
 @pytest.mark.parametrize("N,d", [(2, 3), (3, 1), (37, 2), (64, 3), (65, 3), (300, 3),
                                  (1000, 4), (1100, 3)])
@@ -107,9 +108,8 @@ def test_stress_against_oracle(layout, rho, det, N, d):
     torch.cuda.synchronize()
     L64, g64 = oedm.stress_grad64(X, delta)
     D64 = oedm.edm64_packed(X)
-    ts = rho if rho else 128  # the bound of the larger tile covers both
-    bound = max(_loss_bound(D64, delta, L64, N, ts, det),
-                _loss_bound(D64, delta, L64, N, 64, det))
+    # rho = 0: the bound of whichever tile the autotuner picked
+    bound = max(_loss_bound(D64, delta, L64, N, ts, det) for ts in ((rho,) if rho else TILES))
     got = float(loss.item())
     assert abs(got - L64) <= bound, f"L {got} vs {L64}, bound {bound}"
     _check_grad(dX.cpu().numpy(), g64, f"{layout} N={N} d={d} rho={rho} det={det}")
@@ -124,7 +124,7 @@ def test_stress_deterministic_bits_and_workspace_reuse(layout):
     dd = _device_targets(delta, N, layout)
     ws = torch.empty(tdmap.tdmap_workspace_size(tdmap.OP_STRESS, N, d, 0, 0, 1),
                      dtype=torch.uint8, device="cuda")
-    for rho in (64, 128):
+    for rho in TILES:
         ws.fill_(0xFF)  # stale partials from another call must not leak in
         l1, g1 = tdmap.stress_backward(Xd, dd, layout=layout, rho=rho, workspace=ws)
         l1, g1 = l1.clone(), g1.clone()
@@ -141,7 +141,7 @@ def test_stress_strict_equals_packed_bits():
     N, d = 777, 3
     X, delta = _targets(N, d, seed=5)
     Xd = torch.from_numpy(X).cuda()
-    for rho in (64, 128):
+    for rho in TILES:
         lp, gp = tdmap.stress_backward(Xd, _device_targets(delta, N, "packed"), rho=rho)
         ls, gs = tdmap.stress_backward(Xd, _device_targets(delta, N, "strict"), layout="strict",
                                        rho=rho)
@@ -212,7 +212,7 @@ def test_stress_workload_full_size():
     Xd = torch.from_numpy(X).cuda()
     dl = torch.from_numpy(delta32).cuda()
     for det in (True, False):
-        for rho in (64, 128):
+        for rho in TILES:
             loss, dX = tdmap.stress_backward(Xd, dl, rho=rho, deterministic=det)
             torch.cuda.synchronize()
             nb = -(-N // rho)
