@@ -52,7 +52,9 @@ __global__ void ltm_cell_kernel(EdmArgs a, uint32_t lam0, unsigned long long *co
 template <int D, int LAYOUT, int MODE>
 __global__ void bb_cell_kernel(EdmArgs a, unsigned long long *counts) {
   const uint32_t bx = blockIdx.x, by = blockIdx.y;
-  if constexpr (MODE == kModeStore) {
+  // the timed kernels (EDM and dummy) discard the block at once; the
+  // counting variant keeps every thread for the block-wide count
+  if constexpr (MODE != kModeCount) {
     if (bx > by) return;
   }
   const int64_t i = (int64_t)by * blockDim.y + threadIdx.y;
@@ -159,7 +161,7 @@ __global__ void rec_cell_kernel(EdmArgs a, int mode, uint32_t side, uint32_t nb,
     blk_live = true;
   }
   blk_live = blk_live && R < nb;
-  if constexpr (MODE == kModeStore) {
+  if constexpr (MODE != kModeCount) {
     if (!blk_live) return;
   }
   const int64_t i = (int64_t)R * blockDim.y + threadIdx.y;
