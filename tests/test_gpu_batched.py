@@ -197,7 +197,8 @@ def test_batched_workload_full_size():
     # every persistent walk (linear sweep, 64- and 128-cell tiles) writes
     # the same bits
     other = torch.empty(total, dtype=torch.float32, device="cuda")
-    chosen = tdmap.tdmap_tuned_rho(tdmap.OP_BATCHED, 0, 0, 3, 4096)
+    chosen = tdmap.tdmap_tuned_rho(tdmap.OP_BATCHED, 0, int(po[-1]) // 4096, 3, 4096)
+    assert chosen in (1, 64, 128)
     for rho in (1, 64, 128):
         if rho == chosen:
             continue
@@ -216,3 +217,35 @@ def test_batched_workload_full_size():
         ref = np.concatenate(native.edm_rows(pts, range(len(pts))))
         got = buf[oo[s]: oo[s + 1]].cpu().numpy()
         _check_rel(got, ref, f"set {s} (n={sizes[s]})")
+
+
+def test_batched_tuner_keys_on_set_size():
+    # two batches with the same number of sets but sizes in different ranges
+    # are tuned apart: a decision made on small sets is not reused for large
+    # ones
+    _require_gpu()
+    tdmap.tdmap_autotune_reset()
+    S = 32
+    batches = {}
+    for name, lo, hi in (("small", 8, 16), ("large", 600, 1200)):
+        data = synth.batched_sets(S, lo, hi, 3, seed=41 + lo)
+        batches[name] = data
+    mean = {k: int(v["point_off"][-1]) // S for k, v in batches.items()}
+    assert mean["small"].bit_length() != mean["large"].bit_length()
+
+    def run(data):
+        Xd = torch.from_numpy(data["X"]).cuda()
+        pod = torch.from_numpy(data["point_off"]).cuda()
+        ood = torch.from_numpy(data["out_off"]).cuda()
+        D = tdmap.edm_batched(Xd, pod, ood, rho=0)
+        torch.cuda.synchronize()
+        return D
+
+    run(batches["small"])
+    assert tdmap.tdmap_tuned_rho(tdmap.OP_BATCHED, 0, mean["small"], 3, S) in (1, 64, 128)
+    assert tdmap.tdmap_tuned_rho(tdmap.OP_BATCHED, 0, mean["large"], 3, S) == 0
+    D = run(batches["large"])
+    assert tdmap.tdmap_tuned_rho(tdmap.OP_BATCHED, 0, mean["large"], 3, S) in (1, 64, 128)
+    data = batches["large"]
+    ref = oedm.edm64_batched(data["X"], data["point_off"])
+    _check_rel(D.cpu().numpy(), ref, "large batch after tuning")

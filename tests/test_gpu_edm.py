@@ -340,6 +340,24 @@ def test_big_sampled_rows_against_oracle(big):
         assert np.all(got[r].view(np.int32)[i + 1:] == SENTINEL), f"row {i} upper"
 
 
+def test_big_whole_triangle_against_oracle(big):
+    # every cell of the 30000-point triangle of the benchmark's launch,
+    # compared in bands of 2000 rows against the C oracle (FP64)
+    X, Xd, ref = big
+    N = X.shape[0]
+    checked = 0
+    for r0 in range(0, N, 2000):
+        r1 = min(N, r0 + 2000)
+        band = ref[r0:r1].cpu().numpy()
+        rows = np.arange(r0, r1)
+        lower = np.arange(N)[None, :] <= rows[:, None]
+        got = band[lower]  # row-major: the packed cells of rows r0 .. r1-1
+        exp = np.concatenate(native.edm_rows(X, rows))
+        _check_rel(got, exp, f"rows {r0}..{r1 - 1}")
+        checked += got.size
+    assert checked == N * (N + 1) // 2
+
+
 def test_big_upper_triangle_untouched(big):
     X, Xd, ref = big
     N = X.shape[0]
