@@ -197,6 +197,35 @@ int tdmap_gram_recompute_count(const float *X, int64_t N, int32_t d, int64_t ldx
                                void *stream);
 
 /*
+ * The Gram-form EDM without a workspace argument, for callers that cannot
+ * allocate device memory: code under stream capture, serving loops and
+ * harnesses that forbid allocation.  It computes what tdmap_edm computes
+ * for the same X, N, d, ldx, D, precision and rho with layout TDMAP_PACKED
+ * and strategy TDMAP_LTM (the same kernels, bitwise the same output), but
+ * keeps the BF16 copy of the points and their norms in a static device
+ * array of TDMAP_NOALLOC_SCRATCH_BYTES that each GPU holds from the
+ * library's first call there until the process ends.  It allocates no
+ * memory and makes no allocating call.
+ *   X, N, d, ldx, D  as for tdmap_edm (D packed, any 4-byte alignment).
+ *   precision        TDMAP_BF16_GRAM or TDMAP_BF16X3_GRAM.
+ *   rho              128 or 256 picks the kernel; 0 takes the autotuner's
+ *                    decision if tdmap_edm has already tuned this
+ *                    configuration, else 256.  It never times candidates.
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents: calls that can overlap on one GPU (several streams or
+ * host threads) race on it and must be serialised by the caller.
+ * Errors: INVALID as for tdmap_edm or for another precision; UNSUPPORTED for
+ * rho other than 0, 128, 256, for sizes past the kernels' 32-bit block
+ * index, or when tdmap_workspace_size(TDMAP_OP_EDM, N, d, 0, rho,
+ * precision) exceeds TDMAP_NOALLOC_SCRATCH_BYTES (32 MiB: N = 100000 with
+ * d = 64 fits in both precisions); HIP if the array's device address cannot
+ * be taken or a launch fails.
+ */
+#define TDMAP_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int tdmap_edm_gram_noalloc(const float *X, int64_t N, int32_t d, int64_t ldx,
+                           float *D, int32_t precision, int32_t rho, void *stream);
+
+/*
  * Gradient through the EDM: given dD_ij = dL/dD_ij for the cells of the
  * triangle, writes dX_i = sum_{j<i} dD_ij (x_i - x_j)/D_ij
  *                       - sum_{k>i} dD_ki (x_k - x_i)/D_ki,

@@ -235,6 +235,8 @@ int gram_prepare(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, in
 
 }  // namespace
 
+int tdmap::record_hip_error(hipError_t e, const char *where) { return hip_fail(e, where); }
+
 extern "C" {
 
 const char *tdmap_status_string(int32_t status) {

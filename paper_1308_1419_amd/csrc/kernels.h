@@ -115,6 +115,10 @@ hipError_t launch_sweep(const EdmArgs &a);
 // per CU, each owning one contiguous stretch of the output).
 hipError_t launch_batched_sweep(const BatchArgs &a);
 
+// Keeps the HIP message of a failed call for tdmap_last_error() and
+// returns TDMAP_ERR_HIP.
+int record_hip_error(hipError_t e, const char *where);
+
 // Fill n floats with a value (a kernel, not a memset, so it can sit in a
 // captured graph).
 hipError_t launch_fill(float *p, uint64_t n, float v, hipStream_t stream);

@@ -70,6 +70,7 @@ def _load() -> ctypes.CDLL:
         "tdmap_edm_batched": ([vp, i32, i32, vp, vp, vp, i32, vp, sz, vp], ctypes.c_int),
         "tdmap_gram_recompute_count": ([vp, i64, i32, i64, vp, i32, i32, vp, sz, vp, vp],
                                        ctypes.c_int),
+        "tdmap_edm_gram_noalloc": ([vp, i64, i32, i64, vp, i32, i32, vp], ctypes.c_int),
         "tdmap_workspace_size": ([i32, i64, i32, i32, i32, i32], sz),
         "tdmap_waste_counts": ([i32, i64, i32, vp], ctypes.c_int),
         "tdmap_count_waste": ([i32, i64, i32, vp, vp], ctypes.c_int),
@@ -91,6 +92,7 @@ def _load() -> ctypes.CDLL:
 EXPORTED = (
     "tdmap_map_blocks", "tdmap_map_blocks_nodiag", "tdmap_edm", "tdmap_edm_backward",
     "tdmap_stress_backward", "tdmap_edm_batched", "tdmap_gram_recompute_count",
+    "tdmap_edm_gram_noalloc",
     "tdmap_workspace_size", "tdmap_waste_counts", "tdmap_count_waste",
     "tdmap_map_blocks_variant", "tdmap_dummy", "tdmap_stream_fill",
     "tdmap_tuned_rho", "tdmap_autotune_reset", "tdmap_status_string",
@@ -315,6 +317,12 @@ def dummy(strategy: str, N: int, rho: int, variant: int = 0, sink=None):
         sink = torch.zeros(1, dtype=torch.int32, device="cuda")
     tdmap_dummy(STRATEGIES[strategy], variant, N, rho, 0xFFFFFFFF, sink.data_ptr(), _stream())
     return sink
+
+
+def tdmap_edm_gram_noalloc(X: int, N: int, d: int, ldx: int, D: int, precision: int,
+                           rho: int, stream: int) -> None:
+    _check(_load().tdmap_edm_gram_noalloc(X, N, d, ldx, D, precision, rho, stream),
+           "tdmap_edm_gram_noalloc")
 
 
 def edm(X, layout: str = "full", strategy: str = "ltm", rho: int = 0,
