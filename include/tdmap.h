@@ -147,7 +147,7 @@ int tdmap_map_blocks_nodiag(uint64_t lambda0, uint64_t count, uint32_t *ij, void
  *   precision TDMAP_FP32 for every strategy; TDMAP_BF16_GRAM and
  *            TDMAP_BF16X3_GRAM only with TDMAP_LTM, TDMAP_PACKED and rho = 0,
  *            128 or 256 (128: eight-wave work-groups, each over two 128 x 128
- *            tiles side by side; 256: four-wave work-groups, each over a
+ *            tiles side by side; 256: eight-wave work-groups, each over a
  *            32-row strip of a 256 x 256 tile, the strips of a tile row taken
  *            strip by strip across the row; 0: the autotuner's choice
  *            between the two).  Both kernels compute every 32 x 32 block with

@@ -79,6 +79,9 @@ __global__ __launch_bounds__(256) void gram_prologue_kernel(const float *__restr
 // (d/8 + 6) units of roundoff.
 __device__ __forceinline__ float exact_dist(const float *__restrict__ X, int64_t ldx, int d, int64_t i,
                                          int64_t j) {
+  // a point's distance to itself is exactly 0: the diagonal, most of the
+  // recomputed cells, needs no loads
+  if (i == j) return 0.0f;
   float s[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) s[u] = 0.0f;
@@ -343,35 +346,44 @@ __global__ __launch_bounds__(512, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
 }
 
 // ---------------------------------------------------------------------------
-// strip kernel: four waves, one 32-row strip of a 256 x 256 tile
+// strip kernel: eight waves, one 32-row strip of a 256 x 256 tile
 // ---------------------------------------------------------------------------
 
 // Tile row I (256 rows) is cut into kStripsPerTile strips of 32 rows and a
-// work-group computes one strip of one tile, 32 x 256 cells; wave q owns the
-// columns [64 q, 64 q + 64) (two 32 x 32 accumulators).  The strips of tile
-// row I are numbered u = 0 .. 8 (I + 1) - 1 and taken in column groups of
-// `group` tiles: group outer, strip next, tile column inner.  With one group
-// per tile row the work-groups in flight write a few whole 32-row bands of
-// the packed triangle (one compact window of addresses per XCD, as in the
-// FP32 strips); a narrower group keeps the group's BF16 column points in L2
-// across its strips.  The distances go through LDS (one work-group barrier)
-// and leave as whole packed rows: wave q writes rows q, q + 4, ..., each
-// with four 4-byte store instructions of 256 contiguous bytes (lane l owns
-// columns l + 64 c), or (kStripStore16) one 16-byte store instruction of
-// the aligned chunks plus the partial chunks at both ends, gathered over the
-// wave's rows.
+// work-group computes one strip of one tile, 32 x 256 cells.  The strips of
+// tile row I are numbered u = 0 .. 8 (I + 1) - 1 and taken in column groups
+// of kStripGroup tiles: group outer, strip next, tile column inner, so the
+// work-groups in flight write a few 32-row bands of the packed triangle (a
+// compact window of addresses) while a group's BF16 column points stay in
+// L2 across its 8 strips.
+//
+// Operands: the strip's 32 row points and 256 column points are staged in
+// LDS with coalesced 16-byte loads, 128 bytes per point and pass (64 BF16
+// features, or 32 high and 32 low parts in split mode; larger feature
+// counts take several passes).  The 16-byte chunk c of staged row r sits at
+// chunk c ^ ((r / 2) mod 8) of its row, so that both the coalesced writes
+// and the MFMA operand reads (32 rows, one chunk each) hit every LDS bank
+// once per 16 lanes.  Wave q computes the 32 x 32 block of columns
+// [32 q, 32 q + 32) with the products of gram_products in the same order.
+//
+// Output: the distances of the strip are staged in LDS (over the operand
+// area) and each wave writes whole packed rows q, q + 8, q + 16, q + 24:
+// lane l owns columns l + 64 c and every 4-byte store instruction writes 256
+// contiguous bytes.  The LDS footprint (37 KB) leaves four work-groups per
+// CU.
 constexpr int kStripRows = 32;
 constexpr int kStripsPerTile = 256 / kStripRows;
-constexpr int kStripPitch = 264;  // LDS row pitch: rows r and r + 4 land 32 banks apart
-// column group (tiles) and store form of the strip kernel
-constexpr uint32_t kStripGroup = 0xffffffffu;
-constexpr bool kStripStore16 = false;
+constexpr int kStripWaves = 8;
+constexpr int kStripOpRows = kStripRows + 256;  // staged operand rows
+constexpr int kStripOpBytes = 128;              // bytes per staged row and pass
+constexpr int kStripPitch = 260;                // floats per staged output row
+constexpr uint32_t kStripGroup = 8;
+static_assert(kStripRows * kStripPitch * 4 <= kStripOpRows * kStripOpBytes,
+              "the staged output overlays the operand area");
 
-template <bool SPLIT, int KPC, bool COUNT>
-__global__ __launch_bounds__(256) void gram_strip_kernel(GramArgs a, uint32_t w0, uint32_t nblk,
-                                                         uint32_t group) {
-  const uint32_t w = w0 + xcd_contiguous(blockIdx.x, nblk);
-  uint32_t I, Jt;
+__device__ __forceinline__ void strip_order(uint32_t w, uint32_t group, uint32_t &I, uint32_t &k,
+                                            uint32_t &J) {
+  uint32_t Jt;
   g_lambda(w / kStripsPerTile, I, Jt);
   // u: this work-group's place among the 8 (I + 1) strips of tile row I
   const uint32_t u = kStripsPerTile * Jt + w % kStripsPerTile;
@@ -379,7 +391,6 @@ __global__ __launch_bounds__(256) void gram_strip_kernel(GramArgs a, uint32_t w0
   const uint32_t gs = group < ntile ? group : ntile;
   const uint32_t nfull = ntile / gs;
   const uint32_t span = gs * kStripsPerTile;
-  uint32_t k, J;
   if (u < nfull * span) {
     const uint32_t g = u / span, r = u - g * span;
     k = r / gs;
@@ -390,66 +401,113 @@ __global__ __launch_bounds__(256) void gram_strip_kernel(GramArgs a, uint32_t w0
     k = r / rem;
     J = nfull * gs + (r - k * rem);
   }
+}
+
+// Byte offset of 16-byte chunk c of staged operand row r.
+__device__ __forceinline__ int strip_chunk(int r, int c) {
+  return r * kStripOpBytes + ((c ^ ((r >> 1) & 7)) << 4);
+}
+
+template <bool SPLIT, int KPC, bool COUNT>
+__global__ __launch_bounds__(kStripWaves * 64) void gram_strip_kernel(GramArgs a, uint32_t w0,
+                                                                      uint32_t nblk) {
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  __shared__ __align__(16) unsigned char ops[kStripOpRows * kStripOpBytes];
+  __shared__ float nrow[kStripRows];
+  float *st = reinterpret_cast<float *>(ops);  // after the products
+  const uint32_t w = w0 + xcd_contiguous(blockIdx.x, nblk);
+  uint32_t I, k, J;
+  strip_order(w, kStripGroup, I, k, J);
   const int64_t N = a.N;
   const int64_t r0 = (int64_t)I * 256 + (int64_t)k * kStripRows;
   if (r0 >= N) return;  // a strip past the last point (uniform)
   const int64_t c0 = (int64_t)J * 256;
   const bool diag = I == J;
-  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int l = threadIdx.x & 63;
+  const int t = threadIdx.x;
+  const int q = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int l = t & 63;
   const int lr = l & 31;
+  const int hl = l >> 5;
   const int KP = KPC ? KPC : a.KP;
-  const int bsh = (int)((reinterpret_cast<uintptr_t>(a.D) >> 2) & 3);
-  // LDS position of column c of strip row r: shifted so that the 16-byte
-  // store chunks are aligned LDS reads (16-byte form only)
-  auto shift = [&](int r) { return kStripStore16 ? (row_shift(r) + bsh) & 3 : 0; };
+  if (t < kStripRows) nrow[t] = a.nrm[r0 + t];
+  const float ncol = a.nrm[c0 + 32 * q + lr];
 
-  float nr[16];
+  f32x16 acc;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) nr[v] = a.nrm[r0 + acc_row(v, l)];
-  int64_t cols[2];
-  bool live[2];
-  float nc[2];
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  // features per pass: 64, or 32 high + 32 low parts
+  constexpr int kFpp = SPLIT ? 32 : 64;
+  constexpr int kMaxLoads = (kStripOpRows * kStripOpBytes / 16 + kStripWaves * 64 - 1) / (kStripWaves * 64);
+  for (int k0 = 0; k0 < KP; k0 += kFpp) {
+    const int nf = KP - k0 < kFpp ? KP - k0 : kFpp;  // a multiple of 16
+    const int cpr = nf >> 3;                         // chunks per row and part
+    const int per_part = kStripOpRows * cpr;
+    const int total = per_part * (SPLIT ? 2 : 1);
+    u4 v[kMaxLoads];
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    const int cb = 64 * q + 32 * b;  // block column within the tile
-    cols[b] = c0 + cb;
-    nc[b] = a.nrm[c0 + cb + lr];
-    // on a diagonal tile, blocks right of the strip's last row are above
-    // the diagonal
-    live[b] = !diag || cb < kStripRows * ((int)k + 1);
-  }
-  f32x16 acc[2];
-  gram_products<SPLIT, KPC, 2>(a, KP, r0, cols, live, acc);
-
-  __shared__ __align__(16) float st[kStripRows][kStripPitch];
-  bool any = false;
-#pragma unroll
-  for (int b = 0; b < 2; ++b) {
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int rr = acc_row(v, l);
-      const float g = gram_value(acc[b][v], nr[v], nc[b]);
-      any |= g < 0.0f;
-      st[rr][64 * q + 32 * b + lr + shift(rr)] = g;
+    for (int m = 0; m < kMaxLoads; ++m) {
+      const int e = t + kStripWaves * 64 * m;
+      if (e < total) {
+        const int part = SPLIT ? (e >= per_part) : 0;
+        const int e2 = e - part * per_part;
+        const int row = e2 / cpr, c = e2 - row * cpr;
+        const int64_t g = row < kStripRows ? r0 + row : c0 + (row - kStripRows);
+        const uint16_t *src = (SPLIT && part) ? a.Xlo : a.Xb;
+        v[m] = *reinterpret_cast<const u4 *>(src + g * KP + k0 + 8 * c);
+      }
     }
+#pragma unroll
+    for (int m = 0; m < kMaxLoads; ++m) {
+      const int e = t + kStripWaves * 64 * m;
+      if (e < total) {
+        const int part = SPLIT ? (e >= per_part) : 0;
+        const int e2 = e - part * per_part;
+        const int row = e2 / cpr, c = e2 - row * cpr;
+        *reinterpret_cast<u4 *>(ops + strip_chunk(row, c + 4 * part)) = v[m];
+      }
+    }
+    __syncthreads();
+    // k-steps of 16 features: lane (lr, hl) reads chunk 2 ks + hl of its
+    // row (split: the low parts are chunks 4 + 2 ks + hl)
+    const int ra = lr, rb = kStripRows + 32 * q + lr;
+    for (int ks = 0; ks < (nf >> 4); ++ks) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8 *>(ops + strip_chunk(ra, 2 * ks + hl));
+      const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(ops + strip_chunk(rb, 2 * ks + hl));
+      if constexpr (SPLIT) {
+        const bf16x8 al = *reinterpret_cast<const bf16x8 *>(ops + strip_chunk(ra, 4 + 2 * ks + hl));
+        const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(ops + strip_chunk(rb, 4 + 2 * ks + hl));
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bv, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bl, acc, 0, 0, 0);
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    }
+    __syncthreads();  // the operands are read: the next pass or the output may overwrite them
+  }
+
+  // epilogue: the wave's 32 x 32 block into the staged output; pairs below
+  // the threshold are marked and recomputed afterwards (rare: the diagonal,
+  // which needs no loads, and near-duplicate pairs)
+  const int col = 32 * q + lr;
+  uint32_t rflag = 0;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int rr = acc_row(v, l);
+    const float e = acc[v];  // (copied out: a bit cast of a vector element is avoided)
+    const float g = gram_value(e, nrow[rr], ncol);
+    rflag |= (uint32_t)(g < 0.0f) << v;
+    st[rr * kStripPitch + col] = g < 0.0f ? 0.0f : g;
   }
   uint32_t nrec = 0;
-  if (any) {
-    // rare: the diagonal and near-duplicate pairs, exact FP32 difference
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
+  if (rflag != 0) {
+#pragma unroll 1
+    for (int v = 0; v < 16; ++v) {
+      if ((rflag >> v) & 1u) {
         const int rr = acc_row(v, l);
-        const int c = 64 * q + 32 * b + lr;
-        if (st[rr][c + shift(rr)] < 0.0f) {
-          const int64_t i = r0 + rr;
-          const int64_t j = c0 + c;
-          const bool cell = i < N && j <= i;
-          if (COUNT) nrec += cell;
-          st[rr][c + shift(rr)] = cell ? exact_dist(a.X, a.ldx, a.d, i, j) : 0.0f;
-        }
+        const int64_t i = r0 + rr;
+        const int64_t j = c0 + col;
+        const bool cell = i < N && j <= i;
+        if (COUNT) nrec += cell;
+        st[rr * kStripPitch + col] = cell ? exact_dist(a.X, a.ldx, a.d, i, j) : 0.0f;
       }
     }
   }
@@ -461,49 +519,26 @@ __global__ __launch_bounds__(256) void gram_strip_kernel(GramArgs a, uint32_t w0
   float *__restrict__ outb = a.D + tri64((uint64_t)r0) + (uint64_t)c0;
   const uint32_t r0u = (uint32_t)r0;
   auto row_off = [&](uint32_t r) { return r * r0u + ((r * (r + 1)) >> 1); };
-  const bool interior = !diag && r0 + kStripRows <= N;
-  if (interior && kStripStore16) {
+  if (!diag && r0 + kStripRows <= N) {
 #pragma unroll
-    for (int m = 0; m < kStripRows / 4; ++m) {
-      const int r = q + 4 * m;
-      const int sh = shift(r);
-      if (l > 0 || sh == 0) {
-        const f4 v4 = *reinterpret_cast<const f4 *>(&st[r][4 * l]);
-        *reinterpret_cast<f4 *>(outb + row_off(r) - sh + 4 * l) = v4;
-      }
-    }
-    // the 4 - sh head cells and sh tail cells of the wave's 8 rows, one
-    // cell per lane
-    if (l < 32) {
-      const int r = q + 4 * (l >> 2);
-      const int c4 = l & 3;
-      const int sh = shift(r);
-      if (sh != 0) {
-        const int c = c4 < 4 - sh ? c4 : 252 + c4;
-        outb[row_off(r) + c] = st[r][c + sh];
-      }
-    }
-  } else if (interior) {
-#pragma unroll
-    for (int m = 0; m < kStripRows / 4; ++m) {
-      const int r = q + 4 * m;
+    for (int m = 0; m < kStripRows / kStripWaves; ++m) {
+      const int r = q + kStripWaves * m;
       float *o = outb + row_off(r);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) o[l + 64 * c] = st[r][l + 64 * c];
+      for (int c = 0; c < 4; ++c) o[l + 64 * c] = st[r * kStripPitch + l + 64 * c];
     }
   } else {
     // diagonal or edge strip: rows below N, cells with j <= i
-    for (int m = 0; m < kStripRows / 4; ++m) {
-      const int r = q + 4 * m;
+    for (int m = 0; m < kStripRows / kStripWaves; ++m) {
+      const int r = q + kStripWaves * m;
       const int64_t i = r0 + r;
       if (i >= N) break;
       const int64_t jmax = diag ? i - c0 : 255;
       float *o = outb + row_off(r);
-      const int sh = shift(r);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const int col = l + 64 * c;
-        if (col <= jmax) o[col] = st[r][col + sh];
+        const int cc = l + 64 * c;
+        if (cc <= jmax) o[cc] = st[r * kStripPitch + cc];
       }
     }
   }
@@ -536,23 +571,22 @@ static void launch_gram_tiles(int KP, dim3 grid, hipStream_t stream, const GramA
 
 template <bool SPLIT, bool COUNT>
 static void launch_gram_strips(int KP, dim3 grid, hipStream_t stream, const GramArgs &a, uint32_t w0) {
-  const dim3 block(256);
-  const uint32_t g = kStripGroup;
+  const dim3 block(kStripWaves * 64);
   switch (KP) {
     case 16:
-      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 16, COUNT>), grid, block, 0, stream, a, w0, grid.x, g);
+      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 16, COUNT>), grid, block, 0, stream, a, w0, grid.x);
       break;
     case 32:
-      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 32, COUNT>), grid, block, 0, stream, a, w0, grid.x, g);
+      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 32, COUNT>), grid, block, 0, stream, a, w0, grid.x);
       break;
     case 64:
-      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 64, COUNT>), grid, block, 0, stream, a, w0, grid.x, g);
+      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 64, COUNT>), grid, block, 0, stream, a, w0, grid.x);
       break;
     case 128:
-      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 128, COUNT>), grid, block, 0, stream, a, w0, grid.x, g);
+      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 128, COUNT>), grid, block, 0, stream, a, w0, grid.x);
       break;
     default:
-      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 0, COUNT>), grid, block, 0, stream, a, w0, grid.x, g);
+      hipLaunchKernelGGL((gram_strip_kernel<SPLIT, 0, COUNT>), grid, block, 0, stream, a, w0, grid.x);
   }
 }
 
@@ -595,7 +629,7 @@ static hipError_t launch_gram_t(const float *X, int64_t N, int d, int64_t ldx, f
   if (ts == 256) {
     const uint64_t nb = (uint64_t)(Npad / 256);
     const uint64_t W = (uint64_t)kStripsPerTile * (nb * (nb + 1) / 2);
-    const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
+    const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / (kStripWaves * 64);
     for (uint64_t w0 = 0; w0 < W; w0 += max_blocks) {
       const uint64_t c = W - w0 < max_blocks ? W - w0 : max_blocks;
       if (split)
