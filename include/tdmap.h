@@ -164,15 +164,16 @@ int tdmap_map_blocks_nodiag(uint64_t lambda0, uint64_t count, uint32_t *ij, void
  *            rho = 0, 1 (LTM), 64, 128 or 256.
  *   workspace device scratch of at least
  *            tdmap_workspace_size(TDMAP_OP_EDM, N, d, 0, rho, precision)
- *            bytes (0 for TDMAP_FP32; may then be NULL).
+ *            bytes, 16-byte aligned (0 for TDMAP_FP32; may then be NULL).
  * Every strategy writes the same cells with the same per-pair arithmetic,
  * so their outputs are bitwise identical.  FP32 results are within a
  * relative 1e-6 of the exact distance of the FP32 inputs (squared distances
  * below 2^-126 excepted), and exactly 0 where x_i == x_j.
- * Errors: INVALID for NULL pointers, N < 0, d < 1, ldx < d, ldd < N (FULL)
- * or an unknown enum; UNSUPPORTED for a (strategy, rho, precision, layout)
- * combination listed above as unavailable, d > 4 with tiled rho, or sizes
- * past the 32-bit block index; WORKSPACE if the workspace is too small.
+ * Errors: INVALID for NULL pointers, N < 0, d < 1, ldx < d, ldd < N (FULL),
+ * an unknown enum or a Gram workspace that is not 16-byte aligned;
+ * UNSUPPORTED for a (strategy, rho, precision, layout) combination listed
+ * above as unavailable, d > 4 with tiled rho, or sizes past the 32-bit block
+ * index; WORKSPACE if the workspace is too small.
  */
 int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx,
               float *D, int64_t ldd, int32_t layout, int32_t strategy,

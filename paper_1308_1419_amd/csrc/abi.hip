@@ -214,6 +214,8 @@ int gram_prepare(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, in
     return TDMAP_ERR_UNSUPPORTED;
   if (workspace == nullptr || ws_bytes < tdmap::gram_workspace_bytes(N, d, split))
     return TDMAP_ERR_WORKSPACE;
+  // the BF16 copies are written and read as 16-byte chunks
+  if ((reinterpret_cast<uintptr_t>(workspace) & 15) != 0) return TDMAP_ERR_INVALID;
   int ts = rho;
   if (ts == 0) {
     const TuneKey key(TDMAP_OP_EDM, strategy, 256 + precision, d, size_bucket(N));

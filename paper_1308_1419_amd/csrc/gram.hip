@@ -49,29 +49,61 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// One thread per padded point: BF16 copy (zero padded) and the squared norm
-// of the represented point; with Xlo != nullptr also the low parts.
+// The BF16 copy (zero padded) and the squared norms of the represented
+// points; with Xlo != nullptr also the low parts.  A thread converts one
+// 8-feature chunk of one point and writes it as one 16-byte store, so
+// consecutive threads write consecutive chunks.  A work-group takes
+// ppb = 256 / cpp whole points (cpp = KP / 8 chunks per point; a point with
+// more than 256 chunks takes a work-group alone, its threads stepping by
+// 256 chunks); the chunk partial sums of a point are then added in chunk
+// order by its first thread.
 __global__ __launch_bounds__(256) void gram_prologue_kernel(const float *__restrict__ X, int64_t N, int d,
                                                             int64_t ldx, uint16_t *__restrict__ Xb,
                                                             uint16_t *__restrict__ Xlo,
                                                             float *__restrict__ nrm, int64_t Npad,
                                                             int KP) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= Npad) return;
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  __shared__ float part[256];
+  const int cpp = KP >> 3;
+  const int ppb = cpp <= 256 ? 256 / cpp : 1;
+  const int t = threadIdx.x;
+  const int pl = cpp <= 256 ? t / cpp : 0;  // the thread's point within the work-group
+  const int64_t p = (int64_t)blockIdx.x * ppb + pl;
+  const bool live = pl < ppb && p < Npad;
   float s = 0.0f;
-  for (int k = 0; k < KP; ++k) {
-    const float v = (p < N && k < d) ? X[p * ldx + k] : 0.0f;
-    const uint16_t b = bf16_rne(v);
-    Xb[p * KP + k] = b;
-    float r = bf16_to_f32(b);
-    if (Xlo != nullptr) {
-      const uint16_t c = bf16_rne(v - r);
-      Xlo[p * KP + k] = c;
-      r += bf16_to_f32(c);
+  if (live) {
+    for (int c = cpp <= 256 ? t - pl * cpp : t; c < cpp; c += 256) {
+      uint16_t hb[8], lb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = 8 * c + u;
+        const float v = (p < N && k < d) ? X[p * ldx + k] : 0.0f;
+        hb[u] = bf16_rne(v);
+        float r = bf16_to_f32(hb[u]);
+        if (Xlo != nullptr) {
+          lb[u] = bf16_rne(v - r);
+          r += bf16_to_f32(lb[u]);
+        }
+        s = __builtin_fmaf(r, r, s);
+      }
+      u4 h, lo;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        h[e] = (uint32_t)hb[2 * e] | ((uint32_t)hb[2 * e + 1] << 16);
+        lo[e] = (uint32_t)lb[2 * e] | ((uint32_t)lb[2 * e + 1] << 16);
+      }
+      *reinterpret_cast<u4 *>(Xb + p * KP + 8 * c) = h;
+      if (Xlo != nullptr) *reinterpret_cast<u4 *>(Xlo + p * KP + 8 * c) = lo;
     }
-    s = __builtin_fmaf(r, r, s);
   }
-  nrm[p] = s;
+  part[t] = s;
+  __syncthreads();
+  if (live && (cpp > 256 ? t == 0 : t == pl * cpp)) {
+    float n = 0.0f;
+    const int m = cpp < 256 ? cpp : 256;
+    for (int c = 0; c < m; ++c) n += part[t + c];
+    nrm[p] = n;
+  }
 }
 
 // FP32 difference form with eight interleaved partial sums combined as a
@@ -621,7 +653,9 @@ static hipError_t launch_gram_t(const float *X, int64_t N, int d, int64_t ldx, f
   uint16_t *Xlo = split ? Xb + (size_t)Npad * KP : nullptr;
   float *nrm = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) +
                                          (size_t)Npad * KP * 2 * (split ? 2 : 1));
-  hipLaunchKernelGGL(gram_prologue_kernel, dim3((uint32_t)((Npad + 255) / 256)), dim3(256), 0, stream,
+  const int cpp = KP / 8;
+  const int64_t ppb = cpp <= 256 ? 256 / cpp : 1;
+  hipLaunchKernelGGL(gram_prologue_kernel, dim3((uint32_t)((Npad + ppb - 1) / ppb)), dim3(256), 0, stream,
                      X, N, d, ldx, Xb, Xlo, nrm, Npad, KP);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

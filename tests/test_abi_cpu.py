@@ -120,6 +120,12 @@ def test_gram_workspace_sizes(lib):
                        Npad * KP * 2 + Npad * 4, None) == tdmap.ERR_WORKSPACE
     assert L.tdmap_edm(8, N, d, d, 16, 0, tdmap.PACKED, 0, 0, 3, 8, 1 << 30, None) \
         == tdmap.ERR_INVALID
+    # the BF16 copies are 16-byte chunks: a workspace off a 16-byte boundary
+    # is refused before any launch, in both precisions and at every tile edge
+    for prec in (tdmap.BF16_GRAM, tdmap.BF16X3_GRAM):
+        for rho in (0, 128, 256):
+            assert L.tdmap_edm(16, N, d, d, 16, 0, tdmap.PACKED, 0, rho, prec, 8, 1 << 30,
+                               None) == tdmap.ERR_INVALID
 
 
 def test_stress_validation_and_workspace(lib):
