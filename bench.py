@@ -498,12 +498,35 @@ def row_mapcost(torch, tdmap, synth):
     return res
 
 
+def row_paper_style(torch, tdmap, synth):
+    """The paper's one-cell-per-thread launches of all five strategies on the
+    30000-point, d = 3 full-layout EDM at rho = 8, 16, 32 (the launches the
+    main step's comparison times), for profiler runs of these kernels."""
+    N, d = 30000, 3
+    X = synth.uniform_points(N, d, seed=synth.workload_seed(2))
+    Xd = torch.from_numpy(X).cuda()
+    D = torch.empty((N, N), dtype=torch.float32, device="cuda")
+    bytes_alg = 4 * N * (N + 1) // 2
+    out = {}
+    for rho in (8, 16, 32):
+        row = {}
+        for s in STRATS:
+            t = _med_ms(lambda s=s: tdmap.edm(Xd, layout="full", strategy=s, rho=rho, out=D),
+                        10, 2)
+            row[s] = {"us": t * 1e3, "hbm_frac": bytes_alg / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        for s in row:
+            row[s]["I_vs_bb"] = row["bb"]["us"] / row[s]["us"]
+        out[f"rho{rho}"] = row
+    return out
+
+
 ROWS = {"edm_n1024_d3_full": row_small, "stress_n20000_d3": row_stress,
         "mapcost_n30000": row_mapcost, "strict_n30000_d3": row_strict,
         "paper_grid_rho16": row_paper_grid,
         "paper_grid_rho16_reduced": row_paper_grid_reduced,
         "gram_n100000_d64_packed": row_gram,
-        "batched_s4096_n64_4096_d3": row_batched}
+        "batched_s4096_n64_4096_d3": row_batched,
+        "paper_style_n30000_d3": row_paper_style}
 DEFAULT_ROWS = ("edm_n1024_d3_full", "mapcost_n30000", "strict_n30000_d3", "stress_n20000_d3",
                 "gram_n100000_d64_packed", "batched_s4096_n64_4096_d3",
                 "paper_grid_rho16_reduced")

@@ -236,7 +236,7 @@ int tdmap_edm_gram_noalloc(const float *X, int64_t N, int32_t d, int64_t ldx,
  *   X      device, N x d FP32, pitch ldx.    dD device, `layout` (pitch ldd;
  *          any of the three layouts).
  *   dX     device, N x d FP32, row pitch d, overwritten.
- *   rho    tile edge: 0 (autotuned), 64, 128 or 256 (256: dD 16-byte aligned).
+ *   rho    tile edge: 0 (autotuned), 64, 128 or 256.
  *   deterministic  1: per-tile partial sums in the workspace, reduced in a
  *          fixed order (bitwise reproducible); 0: partial sums added with
  *          atomics (no workspace, order-dependent last bits).
@@ -381,7 +381,7 @@ int tdmap_dummy(int32_t strategy, int32_t variant, int64_t N, int32_t rho, uint3
 /* Tile edge the autotuner has chosen for a call with rho = 0, or 0 if that
  * configuration has not been tuned yet.  `strategy` and `layout` are those
  * of the call (ignored for TDMAP_OP_BACKWARD, TDMAP_OP_STRESS and
- * TDMAP_OP_BATCHED, except layout 64 for TDMAP_OP_BACKWARD, below); `size`
+ * TDMAP_OP_BATCHED, except as below); `size`
  * is N for TDMAP_OP_EDM, TDMAP_OP_BACKWARD and
  * TDMAP_OP_STRESS, and num_sets for TDMAP_OP_BATCHED, whose `layout` is
  * the mean set size in points (point_off[num_sets] / num_sets, rounded
@@ -389,8 +389,7 @@ int tdmap_dummy(int32_t strategy, int32_t variant, int64_t N, int32_t rho, uint3
  * (op, strategy, layout, d, ceil(log2(size))); for TDMAP_OP_EDM an
  * output that is not 16-byte aligned (or a full-layout pitch that is not a
  * multiple of 4) is tuned apart, under layout + 64, the Gram precisions
- * under layout 256 + precision, and for TDMAP_OP_BACKWARD a dD that is not
- * 16-byte aligned under layout 64. */
+ * under layout 256 + precision. */
 int32_t tdmap_tuned_rho(int32_t op, int32_t strategy, int32_t layout, int32_t d, int64_t size);
 
 /* Forget every autotuner decision. */

@@ -263,7 +263,7 @@ int32_t tdmap_tuned_rho(int32_t op, int32_t strategy, int32_t layout, int32_t d,
   if (op != TDMAP_OP_EDM) strategy = 0;
   if (op == TDMAP_OP_BATCHED)
     layout = size_bucket(layout);  // the mean set size in points
-  else if (op != TDMAP_OP_EDM && !(op == TDMAP_OP_BACKWARD && layout == 64))
+  else if (op != TDMAP_OP_EDM)
     layout = 0;
   return tuned_lookup(TuneKey(op, strategy, layout, d, size_bucket(size)));
 }
@@ -416,8 +416,6 @@ int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx, const 
   if (N > 0 && dX == nullptr) return TDMAP_ERR_INVALID;
   if (rho != 0 && rho != 64 && rho != 128 && rho != 256) return TDMAP_ERR_INVALID;
   if (d > 4) return TDMAP_ERR_UNSUPPORTED;
-  const bool dd_aligned = (reinterpret_cast<uintptr_t>(dD) & 15) == 0;
-  if (rho == 256 && !dd_aligned) return TDMAP_ERR_UNSUPPORTED;
   if (N == 0) return TDMAP_OK;
   const uint64_t nb = ceil_div((uint64_t)N, rho ? (uint64_t)rho : 64);
   if (tri(nb) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
@@ -431,13 +429,10 @@ int tdmap_edm_backward(const float *X, int64_t N, int32_t d, int64_t ldx, const 
                    det ? reinterpret_cast<float *>(workspace) : nullptr, s};
   int ts = rho;
   if (ts == 0) {
-    // TS = 256 needs a 16-byte aligned dD: unaligned calls are tuned apart
-    const TuneKey key(TDMAP_OP_BACKWARD, 0, dd_aligned ? 0 : 64, d, size_bucket(N));
+    const TuneKey key(TDMAP_OP_BACKWARD, 0, 0, d, size_bucket(N));
     ts = tuned_lookup(key);
     if (ts == 0) {
-      std::vector<int> cands{64, 128};
-      if (dd_aligned) cands.push_back(256);
-      ts = autotune(cands, s, [&](int c) { return tdmap::launch_backward(c, a); }, &st);
+      ts = autotune({64, 128, 256}, s, [&](int c) { return tdmap::launch_backward(c, a); }, &st);
       if (st != TDMAP_OK) return st;
       tuned_store(key, ts);
     }

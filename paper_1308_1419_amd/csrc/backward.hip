@@ -272,154 +272,6 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
   }
 }
 
-// TS = 256 variant with 16-byte loads of dD.  Lane l owns columns
-// col0 + 4l .. col0 + 4l + 3 (their points and column sums stay in
-// registers) and a wave reads one tile row per step.  Row i's segment
-// starts at element `first`, sh = first mod 4 past a 16-byte boundary:
-// lane l loads the aligned chunk at first - sh + 4l, and its own four cells
-// are positions sh.. of that chunk followed by positions ..sh-1 of the next
-// lane's chunk (lane 63 loads that one itself).  sh is uniform across the
-// wave, so the realignment is a uniform select plus three lane shuffles.
-// Loads run four rows ahead of the arithmetic.
-template <int D, int LAYOUT, bool DET>
-__global__ __launch_bounds__(256) void edm_bwd_tile256(BwdArgs a, uint32_t lam0) {
-  constexpr int TS = 256;
-  const uint32_t lam = lam0 + xcd_contiguous(blockIdx.x, gridDim.x);
-  uint32_t I, J;
-  g_lambda(lam, I, J);
-  const int t = threadIdx.x;
-  const int w = t >> 6;
-  const int l = t & 63;
-  const int64_t N = a.N;
-  const int64_t row0 = (int64_t)I * TS;
-  const int64_t col0 = (int64_t)J * TS;
-
-  __shared__ float xs[TS * D];
-  __shared__ float rowp[TS * D];
-  __shared__ float colp[4][TS * D];
-  for (int e = t; e < TS * D; e += 256) {
-    const int r = e / D;
-    const int k = e - r * D;
-    const int64_t p = row0 + r;
-    xs[e] = p < N ? a.X[p * a.ldx + k] : 0.0f;
-  }
-  float xj[4][D];
-  bool jok[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t j = col0 + 4 * l + q;
-    jok[q] = j < N;
-#pragma unroll
-    for (int k = 0; k < D; ++k) xj[q][k] = jok[q] ? a.X[j * a.ldx + k] : 0.0f;
-  }
-  float cacc[4][D];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int k = 0; k < D; ++k) cacc[q][k] = 0.0f;
-  __syncthreads();
-
-  const bool diag = I == J;
-  const bool interior = (J < I) && (row0 + TS <= N);
-  constexpr int RB = 4;
-  for (int rb = 0; rb < TS / 4; rb += RB) {
-    f4 cur[RB], ext[RB];
-    int shv[RB];
-    if (interior) {
-#pragma unroll
-      for (int q = 0; q < RB; ++q) {
-        const int64_t i = row0 + (rb + q) * 4 + w;
-        const uint64_t first = out_index<LAYOUT>((uint64_t)i, (uint64_t)col0, a.ldd);
-        shv[q] = (int)(first & 3);
-        const uint64_t A0 = first - (uint64_t)shv[q];
-        cur[q] = *reinterpret_cast<const f4 *>(a.dD + A0 + 4 * l);
-        ext[q] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
-        if (l == 63 && shv[q] != 0) ext[q] = *reinterpret_cast<const f4 *>(a.dD + A0 + 256);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      const int r = (rb + q) * 4 + w;
-      const int64_t i = row0 + r;
-      float g[4];
-      if (interior) {
-        // the next lane's chunk, first three positions
-        float n0 = __shfl_down(cur[q].x, 1, 64);
-        float n1 = __shfl_down(cur[q].y, 1, 64);
-        float n2 = __shfl_down(cur[q].z, 1, 64);
-        if (l == 63) {
-          n0 = ext[q].x;
-          n1 = ext[q].y;
-          n2 = ext[q].z;
-        }
-        switch (shv[q]) {
-          case 0: g[0] = cur[q].x; g[1] = cur[q].y; g[2] = cur[q].z; g[3] = cur[q].w; break;
-          case 1: g[0] = cur[q].y; g[1] = cur[q].z; g[2] = cur[q].w; g[3] = n0; break;
-          case 2: g[0] = cur[q].z; g[1] = cur[q].w; g[2] = n0; g[3] = n1; break;
-          default: g[0] = cur[q].w; g[1] = n0; g[2] = n1; g[3] = n2; break;
-        }
-      } else {
-        const uint64_t base = out_index<LAYOUT>((uint64_t)i, (uint64_t)col0, a.ldd);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int64_t j = col0 + 4 * l + c;
-          const bool ok = i < N && jok[c] && (!diag || j < i);
-          g[c] = ok ? a.dD[base + 4 * l + c] : 0.0f;
-        }
-      }
-      float xi[D];
-#pragma unroll
-      for (int k = 0; k < D; ++k) xi[k] = xs[r * D + k];
-      float rs[D];
-#pragma unroll
-      for (int k = 0; k < D; ++k) rs[k] = 0.0f;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        float diff[D];
-        float s2 = 0.0f;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          diff[k] = xi[k] - xj[c][k];
-          s2 = __builtin_fmaf(diff[k], diff[k], s2);
-        }
-        // g is 0 for every cell outside the strict lower triangle
-        const float cc = s2 > 0.0f ? g[c] * __builtin_amdgcn_rsqf(s2) : 0.0f;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          const float v = cc * diff[k];
-          rs[k] += v;
-          cacc[c][k] -= v;
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < D; ++k) rs[k] = wave_sum(rs[k]);
-      if (l == kSumLane) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) rowp[r * D + k] = rs[k];
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int k = 0; k < D; ++k) colp[w][(4 * l + q) * D + k] = cacc[q][k];
-  __syncthreads();
-
-  for (int e = t; e < TS * D; e += 256) {
-    const float cs = ((colp[0][e] + colp[1][e]) + colp[2][e]) + colp[3][e];
-    if constexpr (DET) {
-      float *dst = a.ws + (uint64_t)lam * 2 * TS * D;
-      dst[e] = rowp[e];
-      dst[TS * D + e] = cs;
-    } else {
-      const int r = e / D;
-      const int k = e - r * D;
-      if (row0 + r < N) atomicAdd(&a.dX[(row0 + r) * D + k], rowp[e]);
-      if (col0 + r < N) atomicAdd(&a.dX[(col0 + r) * D + k], cs);
-    }
-  }
-}
-
 // Deterministic second pass: point p in block B = p / TS collects nb + 1
 // partials: entry t <= B is the row partial of tile (B, t), entry t > B the
 // column partial of tile (B + t - B - 1, B).  The work-group holds G
@@ -513,10 +365,6 @@ __global__ __launch_bounds__(TS * D * bwd_reduce_groups<TS * D>()) void edm_bwd_
   }
 }
 
-// The backward at TS = 256: the 16-byte load kernel above (true), or the
-// 16-lane row-group tile of edm_bwd_tile with eight columns per lane (false).
-constexpr bool kBwd256Vector = true;
-
 template <int TS, int D, int LAYOUT, bool DET>
 static hipError_t launch_bwd_t(const BwdArgs &a) {
   const uint64_t nb = (uint64_t)((a.N + TS - 1) / TS);
@@ -528,13 +376,8 @@ static hipError_t launch_bwd_t(const BwdArgs &a) {
   const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
   for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
     const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
-    if constexpr (TS == 256 && kBwd256Vector) {
-      hipLaunchKernelGGL((edm_bwd_tile256<D, LAYOUT, DET>), dim3((uint32_t)c), dim3(256), 0,
-                         a.stream, a, (uint32_t)l0);
-    } else {
-      hipLaunchKernelGGL((edm_bwd_tile<TS, D, LAYOUT, DET>), dim3((uint32_t)c), dim3(256), 0,
-                         a.stream, a, (uint32_t)l0);
-    }
+    hipLaunchKernelGGL((edm_bwd_tile<TS, D, LAYOUT, DET>), dim3((uint32_t)c), dim3(256), 0,
+                       a.stream, a, (uint32_t)l0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (DET) {
@@ -643,10 +486,7 @@ hipError_t launch_backward(int ts, const BwdArgs &a) {
   switch (ts) {
     case 64: return launch_bwd_ts<64>(a);
     case 128: return launch_bwd_ts<128>(a);
-    case 256:
-      // 16-byte loads need a 16-byte aligned dD
-      if ((reinterpret_cast<uintptr_t>(a.dD) & 15) != 0) return hipErrorInvalidValue;
-      return launch_bwd_ts<256>(a);
+    case 256: return launch_bwd_ts<256>(a);
     default: return hipErrorInvalidValue;
   }
 }

@@ -93,9 +93,10 @@ def test_backward_deterministic_bitwise():
         assert torch.equal(a.view(torch.int32), b.view(torch.int32))
 
 
-def test_backward_unaligned_dD_pointer():
-    # the 16-byte-load tile needs an aligned dD; an offset view is refused
-    # for rho = 256 and handled by the other tiles under autotuning
+@pytest.mark.parametrize("rho", [0, 64, 128, 256])
+def test_backward_unaligned_dD_pointer(rho):
+    # every tile reads dD with 4-byte loads: a view one float past a 16-byte
+    # boundary gives the gradient of the same values
     _require_gpu()
     N = 700
     X = synth.uniform_points(N, 3, seed=14)
@@ -104,16 +105,14 @@ def test_backward_unaligned_dD_pointer():
     buf[1:] = torch.from_numpy(dD).cuda()
     view = buf[1:]
     Xd = torch.from_numpy(X).cuda()
-    with pytest.raises(tdmap.TdmapError):
-        tdmap.edm_backward(Xd, view, rho=256, deterministic=True)
-    got = tdmap.edm_backward(Xd, view, rho=0, deterministic=True)
+    got = tdmap.edm_backward(Xd, view, rho=rho, deterministic=True)
     torch.cuda.synchronize()
     _check_grad(got.cpu().numpy(), oedm.edm_backward64(X, dD), "unaligned dD")
 
 
-def test_backward_tuned_apart_by_alignment():
-    # the tuner keeps separate decisions for aligned and unaligned dD, so a
-    # 16-byte-load tile chosen for one is never replayed on the other
+def test_backward_tuned_decision_serves_unaligned_dD():
+    # one tuner decision per (d, size) class; a call with an unaligned dD
+    # after a call that tuned on an aligned one replays it correctly
     _require_gpu()
     N, d = 900, 3
     X = synth.uniform_points(N, d, seed=15)
@@ -124,12 +123,12 @@ def test_backward_tuned_apart_by_alignment():
     buf[: oedm.tri(N)] = torch.from_numpy(dD).cuda()
     tdmap.edm_backward(Xd, buf[: oedm.tri(N)], rho=0, deterministic=True)
     torch.cuda.synchronize()
-    assert tdmap.tdmap_tuned_rho(tdmap.OP_BACKWARD, 0, 0, d, N) in (64, 128, 256)
-    assert tdmap.tdmap_tuned_rho(tdmap.OP_BACKWARD, 0, 64, d, N) == 0
+    ts = tdmap.tdmap_tuned_rho(tdmap.OP_BACKWARD, 0, 0, d, N)
+    assert ts in (64, 128, 256)
     buf[1: oedm.tri(N) + 1] = torch.from_numpy(dD).cuda()
     got = tdmap.edm_backward(Xd, buf[1: oedm.tri(N) + 1], rho=0, deterministic=True)
     torch.cuda.synchronize()
-    assert tdmap.tdmap_tuned_rho(tdmap.OP_BACKWARD, 0, 64, d, N) in (64, 128)
+    assert tdmap.tdmap_tuned_rho(tdmap.OP_BACKWARD, 0, 0, d, N) == ts
     _check_grad(got.cpu().numpy(), oedm.edm_backward64(X, dD), "unaligned dD after an aligned tune")
 
 
