@@ -181,6 +181,29 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx,
               void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * One shard of tdmap_edm, the per-device share of a run split over
+ * num_shards devices (or streams): with tdmap_edm's arguments it writes only
+ * the cells of the blocks whose index lies in
+ *   [shard * W / num_shards, (shard + 1) * W / num_shards)
+ * of the launch's block index space of W blocks.  The blocks are placed by
+ * g(lambda) (Sec. II-A, Eq. (2)), so the shards are equal to one block and
+ * need no exchange; the union of all shards' writes is tdmap_edm's output
+ * for the same kernel, bit for bit, and different shards write disjoint
+ * cells.  Every shard must cut the same block space, so the kernel is named:
+ *   strategy  TDMAP_LTM.
+ *   rho       TDMAP_FP32: 64, 128 or 256 (the tiles and strips of tdmap_edm,
+ *             d <= 4); the Gram precisions: 128 or 256.
+ *   shard, num_shards  0 <= shard < num_shards.
+ * A Gram shard rounds the whole of X to BF16 into its own workspace.
+ * Errors: as tdmap_edm; INVALID for a bad shard or num_shards; UNSUPPORTED
+ * for another strategy, rho 0, 1, 8, 16 or 32.
+ */
+int tdmap_edm_shard(const float *X, int64_t N, int32_t d, int64_t ldx,
+                    float *D, int64_t ldd, int32_t layout, int32_t strategy,
+                    int32_t rho, int32_t precision, void *workspace, size_t ws_bytes,
+                    int32_t shard, int32_t num_shards, void *stream);
+
+/*
  * Instrumented Gram-form EDM: the launch tdmap_edm makes for the same
  * arguments (precision TDMAP_BF16_GRAM or TDMAP_BF16X3_GRAM, layout
  * TDMAP_PACKED, strategy TDMAP_LTM; rho 128 or 256 picks the kernel, 0 the

@@ -384,6 +384,41 @@ int tdmap_edm(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int64
   return TDMAP_OK;
 }
 
+int tdmap_edm_shard(const float *X, int64_t N, int32_t d, int64_t ldx, float *D, int64_t ldd,
+                    int32_t layout, int32_t strategy, int32_t rho, int32_t precision,
+                    void *workspace, size_t ws_bytes, int32_t shard, int32_t num_shards,
+                    void *stream) {
+  int st = validate_edm_common(X, N, d, ldx, D, ldd, layout);
+  if (st != TDMAP_OK) return st;
+  if (strategy < TDMAP_LTM || strategy > TDMAP_REC) return TDMAP_ERR_INVALID;
+  if (precision != TDMAP_FP32 && precision != TDMAP_BF16_GRAM && precision != TDMAP_BF16X3_GRAM)
+    return TDMAP_ERR_INVALID;
+  if (num_shards < 1 || shard < 0 || shard >= num_shards) return TDMAP_ERR_INVALID;
+  // every shard must cut the same block space: the kernel is named, never tuned
+  if (strategy != TDMAP_LTM) return TDMAP_ERR_UNSUPPORTED;
+  if (precision != TDMAP_FP32) {
+    if (rho != 128 && rho != 256) return TDMAP_ERR_UNSUPPORTED;
+    int ts = 0;
+    st = gram_prepare(X, N, d, ldx, D, layout, strategy, rho, precision, workspace, ws_bytes,
+                      stream, false, &ts);
+    if (st != TDMAP_OK || N == 0) return st;
+    TD_HIP(tdmap::launch_gram(X, N, d, ldx, D, workspace, precision == TDMAP_BF16X3_GRAM, ts,
+                              (hipStream_t)stream, (uint32_t)shard, (uint32_t)num_shards),
+           "tdmap_edm_shard");
+    return TDMAP_OK;
+  }
+  if (rho != 64 && rho != 128 && rho != 256) return TDMAP_ERR_UNSUPPORTED;
+  if (d > 4) return TDMAP_ERR_UNSUPPORTED;
+  if (N == 0) return TDMAP_OK;
+  const uint64_t nb = ceil_div((uint64_t)N, (uint64_t)rho);
+  if (tri(nb) > 0xffffffffull) return TDMAP_ERR_UNSUPPORTED;
+  tdmap::EdmArgs a{X, N, d, ldx, D, ldd, layout, (hipStream_t)stream};
+  a.shard = (uint32_t)shard;
+  a.nshards = (uint32_t)num_shards;
+  TD_HIP(tdmap::launch_tiled(false, rho, a), "tdmap_edm_shard");
+  return TDMAP_OK;
+}
+
 int tdmap_gram_recompute_count(const float *X, int64_t N, int32_t d, int64_t ldx, float *D,
                                int32_t precision, int32_t rho, void *workspace, size_t ws_bytes,
                                uint64_t *count, void *stream) {

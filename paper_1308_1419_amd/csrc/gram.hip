@@ -644,7 +644,8 @@ bool gram_supported(int64_t N, int ts) {
 
 template <bool COUNT>
 static hipError_t launch_gram_t(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws,
-                                bool split, int ts, unsigned long long *count, hipStream_t stream) {
+                                bool split, int ts, unsigned long long *count, hipStream_t stream,
+                                uint32_t shard = 0, uint32_t nshards = 1) {
   if (N == 0) return hipSuccess;
   const int64_t Npad = gram_npad(N);
   const int KP = (d + 15) / 16 * 16;
@@ -663,9 +664,11 @@ static hipError_t launch_gram_t(const float *X, int64_t N, int d, int64_t ldx, f
   if (ts == 256) {
     const uint64_t nb = (uint64_t)(Npad / 256);
     const uint64_t W = (uint64_t)kStripsPerTile * (nb * (nb + 1) / 2);
+    uint64_t lo, hi;
+    shard_range(W, shard, nshards, lo, hi);
     const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / (kStripWaves * 64);
-    for (uint64_t w0 = 0; w0 < W; w0 += max_blocks) {
-      const uint64_t c = W - w0 < max_blocks ? W - w0 : max_blocks;
+    for (uint64_t w0 = lo; w0 < hi; w0 += max_blocks) {
+      const uint64_t c = hi - w0 < max_blocks ? hi - w0 : max_blocks;
       if (split)
         launch_gram_strips<true, COUNT>(KP, dim3((uint32_t)c), stream, a, (uint32_t)w0);
       else
@@ -677,9 +680,11 @@ static hipError_t launch_gram_t(const float *X, int64_t N, int d, int64_t ldx, f
   if (ts != 128) return hipErrorInvalidValue;
   const uint64_t nb2 = (uint64_t)(Npad / 256);
   const uint64_t T = nb2 * (nb2 + 1);  // two work-groups per 256 x 256 tile
+  uint64_t lo, hi;
+  shard_range(T, shard, nshards, lo, hi);
   const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 512;
-  for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
-    const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
+  for (uint64_t l0 = lo; l0 < hi; l0 += max_blocks) {
+    const uint64_t c = hi - l0 < max_blocks ? hi - l0 : max_blocks;
     if (split)
       launch_gram_tiles<true, COUNT>(KP, dim3((uint32_t)c), stream, a, (uint32_t)l0);
     else
@@ -690,8 +695,8 @@ static hipError_t launch_gram_t(const float *X, int64_t N, int d, int64_t ldx, f
 }
 
 hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws, bool split,
-                       int ts, hipStream_t stream) {
-  return launch_gram_t<false>(X, N, d, ldx, D, ws, split, ts, nullptr, stream);
+                       int ts, hipStream_t stream, uint32_t shard, uint32_t nshards) {
+  return launch_gram_t<false>(X, N, d, ldx, D, ws, split, ts, nullptr, stream, shard, nshards);
 }
 
 hipError_t launch_gram_count(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws,

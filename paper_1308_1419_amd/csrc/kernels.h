@@ -20,7 +20,17 @@ struct EdmArgs {
   uint32_t *sink = nullptr;
   uint32_t never = 0;
   int variant = 0;
+  // LTM tile and strip launches: only the blocks of shard `shard` of
+  // `nshards` equal ranges of the block index space
+  uint32_t shard = 0;
+  uint32_t nshards = 1;
 };
+
+// Block range [lo, hi) of shard s of P over a space of W blocks.
+inline void shard_range(uint64_t W, uint32_t s, uint32_t P, uint64_t &lo, uint64_t &hi) {
+  lo = W * s / P;
+  hi = W * (s + 1) / P;
+}
 
 // g(lambda) for lambda0 .. lambda0 + count - 1 (caller checks the range).
 hipError_t launch_map_blocks(uint64_t lambda0, uint64_t count, uint32_t *ij, hipStream_t stream);
@@ -102,7 +112,7 @@ struct GramArgs {
 size_t gram_workspace_bytes(int64_t N, int d, bool split);
 bool gram_supported(int64_t N, int ts);
 hipError_t launch_gram(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws, bool split,
-                       int ts, hipStream_t stream);
+                       int ts, hipStream_t stream, uint32_t shard = 0, uint32_t nshards = 1);
 // The same launch with every recomputed pair (i, j), j <= i < N, counted
 // into *count (zeroed first).
 hipError_t launch_gram_count(const float *X, int64_t N, int d, int64_t ldx, float *D, void *ws,

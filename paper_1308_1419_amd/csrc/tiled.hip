@@ -287,9 +287,11 @@ static hipError_t launch_band(bool bb, const EdmArgs &a) {
   }
   const uint64_t W = (uint64_t)kBandStrips * (nb * (nb + 1) / 2);
   if (W > 0xffffffffull) return hipErrorInvalidValue;  // w is 32-bit (N above 4 million)
+  uint64_t lo, hi;
+  shard_range(W, a.shard, a.nshards, lo, hi);
   const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
-  for (uint64_t w0 = 0; w0 < W; w0 += max_blocks) {
-    const uint64_t c = W - w0 < max_blocks ? W - w0 : max_blocks;
+  for (uint64_t w0 = lo; w0 < hi; w0 += max_blocks) {
+    const uint64_t c = hi - w0 < max_blocks ? hi - w0 : max_blocks;
     hipLaunchKernelGGL((edm_band_kernel<D, LAYOUT, false, XV>), dim3((uint32_t)c), dim3(256), 0, a.stream,
                        a.X, a.N, a.ldx, a.D, a.ldd, (uint32_t)w0);
     hipError_t e = hipGetLastError();
@@ -312,9 +314,11 @@ static hipError_t launch_tiled_t(bool bb, const EdmArgs &a) {
       return hipGetLastError();
     }
     const uint64_t T = nb * (nb + 1) / 2;
+    uint64_t lo, hi;
+    shard_range(T, a.shard, a.nshards, lo, hi);
     const uint64_t max_blocks = (((uint64_t)1 << 32) - 1) / 256;
-    for (uint64_t l0 = 0; l0 < T; l0 += max_blocks) {
-      const uint64_t c = T - l0 < max_blocks ? T - l0 : max_blocks;
+    for (uint64_t l0 = lo; l0 < hi; l0 += max_blocks) {
+      const uint64_t c = hi - l0 < max_blocks ? hi - l0 : max_blocks;
       hipLaunchKernelGGL((edm_tile_kernel<TS, D, LAYOUT, VEC, false>), dim3((uint32_t)c), dim3(256),
                          0, a.stream, a, (uint32_t)l0);
       hipError_t e = hipGetLastError();

@@ -71,6 +71,8 @@ def _load() -> ctypes.CDLL:
         "tdmap_gram_recompute_count": ([vp, i64, i32, i64, vp, i32, i32, vp, sz, vp, vp],
                                        ctypes.c_int),
         "tdmap_edm_gram_noalloc": ([vp, i64, i32, i64, vp, i32, i32, vp], ctypes.c_int),
+        "tdmap_edm_shard": ([vp, i64, i32, i64, vp, i64, i32, i32, i32, i32, vp, sz, i32, i32, vp],
+                            ctypes.c_int),
         "tdmap_workspace_size": ([i32, i64, i32, i32, i32, i32], sz),
         "tdmap_waste_counts": ([i32, i64, i32, vp], ctypes.c_int),
         "tdmap_count_waste": ([i32, i64, i32, vp, vp], ctypes.c_int),
@@ -92,7 +94,7 @@ def _load() -> ctypes.CDLL:
 EXPORTED = (
     "tdmap_map_blocks", "tdmap_map_blocks_nodiag", "tdmap_edm", "tdmap_edm_backward",
     "tdmap_stress_backward", "tdmap_edm_batched", "tdmap_gram_recompute_count",
-    "tdmap_edm_gram_noalloc",
+    "tdmap_edm_gram_noalloc", "tdmap_edm_shard",
     "tdmap_workspace_size", "tdmap_waste_counts", "tdmap_count_waste",
     "tdmap_map_blocks_variant", "tdmap_dummy", "tdmap_stream_fill",
     "tdmap_tuned_rho", "tdmap_autotune_reset", "tdmap_status_string",
@@ -319,6 +321,14 @@ def dummy(strategy: str, N: int, rho: int, variant: int = 0, sink=None):
     return sink
 
 
+def tdmap_edm_shard(X: int, N: int, d: int, ldx: int, D: int, ldd: int, layout: int,
+                    strategy: int, rho: int, precision: int, workspace: int, ws_bytes: int,
+                    shard: int, num_shards: int, stream: int) -> None:
+    _check(_load().tdmap_edm_shard(X, N, d, ldx, D, ldd, layout, strategy, rho, precision,
+                                   workspace, ws_bytes, shard, num_shards, stream),
+           "tdmap_edm_shard")
+
+
 def tdmap_edm_gram_noalloc(X: int, N: int, d: int, ldx: int, D: int, precision: int,
                            rho: int, stream: int) -> None:
     _check(_load().tdmap_edm_gram_noalloc(X, N, d, ldx, D, precision, rho, stream),
@@ -354,6 +364,40 @@ def edm(X, layout: str = "full", strategy: str = "ltm", rho: int = 0,
     ws_len = workspace.numel() * workspace.element_size() if workspace is not None else 0
     tdmap_edm(X.data_ptr(), N, d, X.stride(0), out.data_ptr(), ldd, lay,
               STRATEGIES[strategy], rho, prec, ws_ptr, ws_len, _stream())
+    return out
+
+
+def edm_shard(X, shard: int, num_shards: int, layout: str = "full", rho: int = 256,
+              precision: str = "fp32", out=None, ldd: Optional[int] = None, workspace=None):
+    """Shard `shard` of `num_shards` of the LTM EDM of X (see tdmap_edm_shard):
+    only that shard's cells of `out` are written (a new output is allocated
+    uninitialised if none is given)."""
+    torch = _torch()
+    X = _points(X)
+    N, d = X.shape
+    lay = LAYOUTS[layout]
+    prec = PRECISIONS[precision]
+    if out is None:
+        if lay == FULL:
+            out = torch.empty((N, N), dtype=torch.float32, device=X.device)
+        elif lay == PACKED_STRICT:
+            out = torch.empty(strict_size(N), dtype=torch.float32, device=X.device)
+        else:
+            out = torch.empty(packed_size(N), dtype=torch.float32, device=X.device)
+    if ldd is None:
+        ldd = out.stride(0) if lay == FULL else 0
+    if lay == FULL:
+        _check_full_buffer(out, "out", N, ldd, X.device)
+    else:
+        _device_tensor(out, "out", torch.float32, X.device,
+                       min_numel=_triangle_cells(N, lay))
+    ws_bytes = tdmap_workspace_size(OP_EDM, N, d, 0, rho, prec)
+    if ws_bytes and workspace is None:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=X.device)
+    ws_ptr = workspace.data_ptr() if workspace is not None else 0
+    ws_len = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    tdmap_edm_shard(X.data_ptr(), N, d, X.stride(0), out.data_ptr(), ldd, lay, LTM, rho, prec,
+                    ws_ptr, ws_len, shard, num_shards, _stream())
     return out
 
 
