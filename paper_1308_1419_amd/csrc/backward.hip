@@ -34,6 +34,15 @@ __device__ __forceinline__ float dpp_move(float v) {
       float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xF, false));
 }
 
+// A lane move inside 16-lane rows whose every source lane exists (quad
+// permutes, the row mirrors): with bound control set, the move folds into
+// the add that consumes it.
+template <int CTRL>
+__device__ __forceinline__ float dpp_row_move(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
   v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
   v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
@@ -53,11 +62,20 @@ constexpr int kBwdLanesPerRow = 16;
 // every lane of the group receives the sum.
 template <int LPR>
 __device__ __forceinline__ float group_sum(float v) {
-  v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-  v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-  v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
-  if constexpr (LPR == 16) v += dpp_move<0x140, 0xF>(v);  // row_mirror
+  v += dpp_row_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_row_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_row_move<0x141>(v);  // row_half_mirror
+  if constexpr (LPR == 16) v += dpp_row_move<0x140>(v);  // row_mirror
   return v;
+}
+
+// Element distance in dD from row i to row i + p (same column), and from
+// row i to row i + 16, in the layout's row-major order.
+template <int LAYOUT>
+__device__ __forceinline__ uint64_t row_gap(uint64_t i, int p, int64_t ldd) {
+  if constexpr (LAYOUT == kLayoutFull) return (uint64_t)p * (uint64_t)ldd;
+  else if constexpr (LAYOUT == kLayoutPacked) return (uint64_t)p * i + (uint64_t)(p * (p + 1) / 2);
+  else return (uint64_t)p * i + (uint64_t)(p * (p - 1) / 2);
 }
 
 // Lane layout of a wave's H x H tile quarter: LPR lanes per row group,
@@ -86,22 +104,23 @@ __device__ __forceinline__ void bwd_quarter_steps(
   constexpr int Q = L::Q;
   constexpr int P = L::P;
   const int64_t N = a.N;
-  auto load_step = [&](int s, float (&g)[P][Q], bool (&okm)[P][Q]) {
+  // row p = 0 of the current step and its element index in dD; the rows
+  // below it follow by row_gap (no multiply by the row per load)
+  int64_t ist = row0 + rq0 + P * rg;
+  uint64_t bst = out_index<LAYOUT>((uint64_t)ist, (uint64_t)cbase, a.ldd);
+  auto load_row = [&](int p, float (&g)[Q], bool (&okm)[Q]) {
+    const int64_t i = ist + p;
+    const float *rp = a.dD + bst + row_gap<LAYOUT>((uint64_t)ist, p, a.ldd);
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int64_t i = row0 + rq0 + 16 * s + P * rg + p;
-      const uint64_t base = out_index<LAYOUT>((uint64_t)i, (uint64_t)cbase, a.ldd);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        if constexpr (INTERIOR) {
-          g[p][q] = a.dD[base + LPR * q];
-          okm[p][q] = true;
-        } else {
-          const int64_t j = cbase + LPR * q;
-          const bool ok = i < N && jok[q] && (!diag || j < i);
-          g[p][q] = ok ? a.dD[base + LPR * q] : 0.0f;
-          okm[p][q] = ok;
-        }
+    for (int q = 0; q < Q; ++q) {
+      if constexpr (INTERIOR) {
+        g[q] = rp[LPR * q];
+        okm[q] = true;
+      } else {
+        const int64_t j = cbase + LPR * q;
+        const bool ok = i < N && jok[q] && (!diag || j < i);
+        g[q] = ok ? rp[LPR * q] : 0.0f;
+        okm[q] = ok;
       }
     }
   };
@@ -109,7 +128,10 @@ __device__ __forceinline__ void bwd_quarter_steps(
   for (int s = 0; s < L::STEPS; ++s) {
     float g[P][Q];
     bool okm[P][Q];
-    load_step(s, g, okm);
+#pragma unroll
+    for (int p = 0; p < P; ++p) load_row(p, g[p], okm[p]);
+    bst += row_gap<LAYOUT>((uint64_t)ist, 16, a.ldd);
+    ist += 16;
     const int rl = rq0 + 16 * s + P * rg;  // tile-local row of p = 0
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -136,10 +158,14 @@ __device__ __forceinline__ void bwd_quarter_steps(
           const float e = s2 * r - g[p][q];
           const bool ok = INTERIOR || okm[p][q];
           lacc = ok ? __builtin_fmaf(e, e, lacc) : lacc;
-          cc = ok ? 2.0f * e * r : 0.0f;
+          // the factor 2 of dL/dD = 2 e is applied to the sums (exact)
+          cc = ok ? e * r : 0.0f;
         } else {
-          // g is 0 for every cell outside the strict lower triangle
-          cc = s2 > 0.0f ? g[p][q] * __builtin_amdgcn_rsqf(s2) : 0.0f;
+          // g is 0 for every cell outside the strict lower triangle; the
+          // select is on the reciprocal (0 at coincident points), so the
+          // load of g is not tied to a branch
+          const float r = s2 > 0.0f ? __builtin_amdgcn_rsqf(s2) : 0.0f;
+          cc = g[p][q] * r;
         }
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -148,10 +174,15 @@ __device__ __forceinline__ void bwd_quarter_steps(
         }
       }
 #pragma unroll
-      for (int k = 0; k < D; ++k) rs[k] = group_sum<LPR>(rs[k]);
+      for (int k = 0; k < D; ++k) {
+        rs[k] = group_sum<LPR>(rs[k]);
+        // keep the last add beside its lane move (it folds into one DPP
+        // add) rather than inside the one-lane store below
+        asm volatile("" : "+v"(rs[k]));
+      }
       if (cg == LPR - 1) {
 #pragma unroll
-        for (int k = 0; k < D; ++k) rowp[(rl + p) * D + k] = rs[k];
+        for (int k = 0; k < D; ++k) rowp[(rl + p) * D + k] = STRESS ? 2.0f * rs[k] : rs[k];
       }
     }
   }
@@ -243,7 +274,8 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-      for (int k = 0; k < D; ++k) colp[rh][(H * ch + cg + LPR * q) * D + k] = cacc[q][k];
+      for (int k = 0; k < D; ++k)
+        colp[rh][(H * ch + cg + LPR * q) * D + k] = STRESS ? 2.0f * cacc[q][k] : cacc[q][k];
   }
   __syncthreads();
 
