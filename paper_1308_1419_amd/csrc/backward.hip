@@ -80,15 +80,18 @@ __device__ __forceinline__ uint64_t row_gap(uint64_t i, int p, int64_t ldd) {
 
 // Lane layout of a wave's H x H tile quarter: LPR lanes per row group,
 // RG = 64 / LPR row groups; lane l = LPR rg + cg owns columns cg + LPR q
-// (q < Q = H / LPR) and, in 16-row step s, rows rq0 + 16 s + P rg + p
-// (p < P = 16 / RG).
+// (q < Q = H / LPR) and, in step s of SR rows, rows rq0 + SR s + P rg + p
+// (p < P = SR / RG).  SR = 8 for TS = 128 and 256 (a lane's 2 x Q block
+// per step keeps TS = 256 at 150 VGPRs, three waves per SIMD; 16-row steps
+// took 216, two waves, and were 4 % slower), 16 for TS = 64.
 template <int TS, int LPR>
 struct BwdLayout {
   static constexpr int H = TS / 2;
   static constexpr int RG = 64 / LPR;
   static constexpr int Q = H / LPR;
-  static constexpr int P = 16 / RG;
-  static constexpr int STEPS = H / 16;
+  static constexpr int SR = TS >= 128 ? 8 : 16;  // rows per step
+  static constexpr int P = SR / RG;
+  static constexpr int STEPS = H / SR;
 };
 
 // STRESS: the loaded values are the targets delta_ij rather than dL/dD_ij;
@@ -130,9 +133,9 @@ __device__ __forceinline__ void bwd_quarter_steps(
     bool okm[P][Q];
 #pragma unroll
     for (int p = 0; p < P; ++p) load_row(p, g[p], okm[p]);
-    bst += row_gap<LAYOUT>((uint64_t)ist, 16, a.ldd);
-    ist += 16;
-    const int rl = rq0 + 16 * s + P * rg;  // tile-local row of p = 0
+    bst += row_gap<LAYOUT>((uint64_t)ist, L::SR, a.ldd);
+    ist += L::SR;
+    const int rl = rq0 + L::SR * s + P * rg;  // tile-local row of p = 0
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       float xi[D], rs[D];
@@ -188,19 +191,19 @@ __device__ __forceinline__ void bwd_quarter_steps(
   }
 }
 
-// TS = 64 or 128.  The four waves split the tile into 2 x 2 quarters of
-// H = TS/2 rows and columns; wave w takes row half w >> 1 and column half
-// w & 1.  Inside a wave, lane l = LPR rg + cg owns columns cg + LPR q
+// TS = 64, 128 or 256.  The four waves split the tile into 2 x 2 quarters
+// of H = TS/2 rows and columns; wave w takes row half w >> 1 and column
+// half w & 1.  Inside a wave, lane l = LPR rg + cg owns columns cg + LPR q
 // (q < Q = H/LPR) of its column half, so one load instruction reads LPR
 // consecutive cells of each of RG = 64/LPR rows, and rows P rg .. P rg + P - 1
-// (P = 16/RG) of each 16-row step.  A lane thus works on a P x Q block of
-// cells per step: the row sums of its rows are reduced over only the LPR
+// (P = SR/RG) of each step of SR rows.  A lane thus works on a P x Q block
+// of cells per step: the row sums of its rows are reduced over only the LPR
 // lanes of its row group (full-rate DPP moves, no broadcasts), and the
 // column sums stay in registers for the whole tile and are reduced over the
 // row groups once at the end.  A step's P x Q loads are issued together
-// before its arithmetic; the next step's are not prefetched, which keeps
-// the register count at four waves per SIMD (measured faster than
-// prefetching at three).
+// before its arithmetic; the next step's are not prefetched (prefetching,
+// also into the registers each row frees, was slower: it costs waves per
+// SIMD and the tiles are not waiting on HBM latency alone).
 template <int TS, int D, int LAYOUT, bool DET, bool STRESS = false>
 __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
   constexpr int LPR = kBwdLanesPerRow;
@@ -306,11 +309,12 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
 
 // Deterministic second pass: point p in block B = p / TS collects nb + 1
 // partials: entry t <= B is the row partial of tile (B, t), entry t > B the
-// column partial of tile (B + t - B - 1, B).  The work-group holds G
-// groups of TS d threads (G = 1024 / (TS d), at most 4); group g takes the
-// entries t = g mod G with eight accumulators (every eighth of its entries,
-// eight loads in flight per thread), and the G group sums are added in
-// group order, so the result does not depend on timing.
+// column partial of tile (B + t - B - 1, B).  A work-group takes 64 points
+// of a block (TS / 64 work-groups per block, so the pass has enough of them
+// in flight) and holds G groups of 64 d threads (G = 1024 / (64 d), at most
+// 4); group g takes the entries t = g mod G with eight accumulators (every
+// eighth of its entries, eight loads in flight per thread), and the G group
+// sums are added in group order, so the result does not depend on timing.
 template <int E>
 constexpr int bwd_reduce_groups() {
   return 1024 / E >= 4 ? 4 : (1024 / E >= 2 ? 2 : 1);
@@ -345,20 +349,23 @@ __device__ __forceinline__ void loss_total(const float *__restrict__ part, uint6
   if (t == 0) loss[0] = buf[0];
 }
 
-// With loss != nullptr (the fused stress pass) one more work-group,
-// blockIdx.x == nb, adds the T per-tile losses.
+constexpr int kReducePoints = 64;  // points per reduce work-group
+
+// With loss != nullptr (the fused stress pass) one more work-group, the
+// last, adds the T per-tile losses.
 template <int TS, int D>
-__global__ __launch_bounds__(TS * D * bwd_reduce_groups<TS * D>()) void edm_bwd_reduce(
-    const float *__restrict__ ws, float *__restrict__ dX, int64_t N, uint32_t nb,
-    const float *__restrict__ ws_loss, uint64_t T, float *__restrict__ loss) {
-  constexpr int G = bwd_reduce_groups<TS * D>();
-  constexpr int E = TS * D;
-  const uint32_t B = blockIdx.x;
-  if (B == nb) {
+__global__ __launch_bounds__(kReducePoints * D * bwd_reduce_groups<kReducePoints * D>()) void
+edm_bwd_reduce(const float *__restrict__ ws, float *__restrict__ dX, int64_t N, uint32_t nb,
+               const float *__restrict__ ws_loss, uint64_t T, float *__restrict__ loss) {
+  constexpr int E = kReducePoints * D;
+  constexpr int G = bwd_reduce_groups<E>();
+  constexpr int S = TS / kReducePoints;  // work-groups per block
+  if (blockIdx.x == nb * S) {
     loss_total<E * G>(ws_loss, T, loss);
     return;
   }
-  const int e = threadIdx.x % E;
+  const uint32_t B = blockIdx.x / S;
+  const int e = (int)(blockIdx.x % S) * E + (int)(threadIdx.x % E);  // element in the block
   const int g = threadIdx.x / E;
   const int64_t p = (int64_t)B * TS + e / D;
   constexpr int STRIDE = 2 * TS * D;
@@ -386,12 +393,13 @@ __global__ __launch_bounds__(TS * D * bwd_reduce_groups<TS * D>()) void edm_bwd_
     if (p < N) dX[(uint64_t)B * TS * D + e] = part;
   } else {
     __shared__ float red[G][E];
-    red[g][e] = part;
+    const int el = threadIdx.x % E;
+    red[g][el] = part;
     __syncthreads();
     if (g == 0 && p < N) {
-      float sum = red[0][e];
+      float sum = red[0][el];
 #pragma unroll
-      for (int q = 1; q < G; ++q) sum += red[q][e];
+      for (int q = 1; q < G; ++q) sum += red[q][el];
       dX[(uint64_t)B * TS * D + e] = sum;
     }
   }
@@ -413,9 +421,9 @@ static hipError_t launch_bwd_t(const BwdArgs &a) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (DET) {
-    hipLaunchKernelGGL((edm_bwd_reduce<TS, D>), dim3((uint32_t)nb),
-                       dim3(TS * D * bwd_reduce_groups<TS * D>()), 0, a.stream, a.ws, a.dX, a.N,
-                       (uint32_t)nb, nullptr, (uint64_t)0, nullptr);
+    hipLaunchKernelGGL((edm_bwd_reduce<TS, D>), dim3((uint32_t)nb * (TS / kReducePoints)),
+                       dim3(kReducePoints * D * bwd_reduce_groups<kReducePoints * D>()), 0, a.stream,
+                       a.ws, a.dX, a.N, (uint32_t)nb, nullptr, (uint64_t)0, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -460,10 +468,10 @@ static hipError_t launch_stress_t(const BwdArgs &a) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (DET) {
-    // nb work-groups for dX and one more for the loss
-    hipLaunchKernelGGL((edm_bwd_reduce<TS, D>), dim3((uint32_t)nb + 1),
-                       dim3(TS * D * bwd_reduce_groups<TS * D>()), 0, a.stream, a.ws, a.dX, a.N,
-                       (uint32_t)nb, a.ws_loss, T, a.loss);
+    // TS / 64 work-groups per block for dX and one more for the loss
+    hipLaunchKernelGGL((edm_bwd_reduce<TS, D>), dim3((uint32_t)nb * (TS / kReducePoints) + 1),
+                       dim3(kReducePoints * D * bwd_reduce_groups<kReducePoints * D>()), 0, a.stream,
+                       a.ws, a.dX, a.N, (uint32_t)nb, a.ws_loss, T, a.loss);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
