@@ -69,6 +69,21 @@ __device__ __forceinline__ float group_sum(float v) {
   return v;
 }
 
+// Sum over the four 16-lane rows of a wave at each position in the row:
+// every lane l receives the sum over lanes l mod 16 + 16 r, r < 4.  The
+// gfx950 lane swaps pair row 0 with 1 and 2 with 3 (16), then the wave's
+// halves (32), in registers (no LDS round trip as with a lane shuffle).
+__device__ __forceinline__ float cross_row_sum(float v) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, v);
+  const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  const uint32_t a0 = a[0], a1 = a[1];  // copied out before the bit casts
+  const float s = __builtin_bit_cast(float, a0) + __builtin_bit_cast(float, a1);
+  const uint32_t w = __builtin_bit_cast(uint32_t, s);
+  const auto b = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+  const uint32_t b0 = b[0], b1 = b[1];
+  return __builtin_bit_cast(float, b0) + __builtin_bit_cast(float, b1);
+}
+
 // Element distance in dD from row i to row i + p (same column), and from
 // row i to row i + 16, in the layout's row-major order.
 template <int LAYOUT>
@@ -264,15 +279,11 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
     if (l == kSumLane) lossp[w] = lacc;
   }
   // column sums over the row groups (lanes cg + LPR rg)
+  static_assert(LPR == 16, "the row-group sum pairs 16-lane rows");
 #pragma unroll
   for (int q = 0; q < Q; ++q)
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      float v = cacc[q][k];
-#pragma unroll
-      for (int m = LPR; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
-      cacc[q][k] = v;
-    }
+    for (int k = 0; k < D; ++k) cacc[q][k] = cross_row_sum(cacc[q][k]);
   if (rg == 0) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
