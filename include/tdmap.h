@@ -253,9 +253,10 @@ int tdmap_edm_gram_noalloc(const float *X, int64_t N, int32_t d, int64_t ldx,
  * Gradient through the EDM: given dD_ij = dL/dD_ij for the cells of the
  * triangle, writes dX_i = sum_{j<i} dD_ij (x_i - x_j)/D_ij
  *                       - sum_{k>i} dD_ki (x_k - x_i)/D_ki,
- * a term being 0 where D = 0; diagonal cells of dD are ignored.  The tiles
- * are enumerated by g(lambda) as in the forward map.  This operation is not
- * in the paper; it differentiates the EDM of Sec. IV, Eq. (17).
+ * a term being 0 where D = 0 (for finite dD); diagonal cells of dD are
+ * ignored.  The tiles are enumerated by g(lambda) as in the forward map.
+ * This operation is not in the paper; it differentiates the EDM of Sec. IV,
+ * Eq. (17).
  *   X      device, N x d FP32, pitch ldx.    dD device, `layout` (pitch ldd;
  *          any of the three layouts).
  *   dX     device, N x d FP32, row pitch d, overwritten.

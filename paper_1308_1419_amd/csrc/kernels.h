@@ -71,10 +71,10 @@ struct BwdArgs {
   float *ws_loss = nullptr;
 };
 
-// Backward over g(lambda) tiles of edge ts (64 or 128); d in 1..4.
+// Backward over g(lambda) tiles of edge ts (64, 128 or 256); d in 1..4.
 size_t backward_workspace_bytes(int64_t N, int d, int ts);
 hipError_t launch_backward(int ts, const BwdArgs &a);
-// Stress loss and its gradient in one pass (ts 64 or 128): the per-tile
+// Stress loss and its gradient in one pass (ts 64, 128 or 256): the per-tile
 // loss partials follow the dX partials in the workspace.
 size_t stress_workspace_bytes(int64_t N, int d, int ts);
 hipError_t launch_stress(int ts, const BwdArgs &a);
