@@ -53,9 +53,9 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// Lanes per row group in the TS = 64 / 128 tiles (16 measured faster than 8:
-// 8 halves the reduction moves per cell but needs three waves per SIMD's
-// worth of registers at TS = 128).
+// Lanes per row group in the tiles (16 measured faster than 8: 8 halves the
+// reduction moves per cell but needed three waves per SIMD's worth of
+// registers at TS = 128).
 constexpr int kBwdLanesPerRow = 16;
 
 // Sum over the LPR lanes of a row group (LPR = 8 or 16 consecutive lanes);
@@ -84,8 +84,8 @@ __device__ __forceinline__ float cross_row_sum(float v) {
   return __builtin_bit_cast(float, b0) + __builtin_bit_cast(float, b1);
 }
 
-// Element distance in dD from row i to row i + p (same column), and from
-// row i to row i + 16, in the layout's row-major order.
+// Element distance in dD from row i to row i + p (same column) in the
+// layout's row-major order; p = SR gives the next step's first row.
 template <int LAYOUT>
 __device__ __forceinline__ uint64_t row_gap(uint64_t i, int p, int64_t ldd) {
   if constexpr (LAYOUT == kLayoutFull) return (uint64_t)p * (uint64_t)ldd;
