@@ -390,9 +390,10 @@ __global__ __launch_bounds__(512, SPLIT ? 3 : 4) void gram_tile_kernel(GramArgs 
 // L2 across its 8 strips.
 //
 // Operands: the strip's 32 row points and 256 column points are staged in
-// LDS with coalesced 16-byte loads, 128 bytes per point and pass (64 BF16
-// features, or 32 high and 32 low parts in split mode; larger feature
-// counts take several passes).  The 16-byte chunk c of staged row r sits at
+// LDS, 128 bytes per point and pass (64 BF16 features, or 32 high and 32
+// low parts in split mode; larger feature counts take several passes), by
+// 16-byte loads straight into LDS when every pass is full, else by
+// coalesced 16-byte loads through registers.  The 16-byte chunk c of staged row r sits at
 // chunk c ^ ((r / 2) mod 8) of its row, so that both the coalesced writes
 // and the MFMA operand reads (32 rows, one chunk each) hit every LDS bank
 // once per 16 lanes.  Wave q computes the 32 x 32 block of columns
@@ -472,30 +473,50 @@ __global__ __launch_bounds__(kStripWaves * 64) void gram_strip_kernel(GramArgs a
   constexpr int kMaxLoads = (kStripOpRows * kStripOpBytes / 16 + kStripWaves * 64 - 1) / (kStripWaves * 64);
   for (int k0 = 0; k0 < KP; k0 += kFpp) {
     const int nf = KP - k0 < kFpp ? KP - k0 : kFpp;  // a multiple of 16
-    const int cpr = nf >> 3;                         // chunks per row and part
-    const int per_part = kStripOpRows * cpr;
-    const int total = per_part * (SPLIT ? 2 : 1);
-    u4 v[kMaxLoads];
-#pragma unroll
-    for (int m = 0; m < kMaxLoads; ++m) {
-      const int e = t + kStripWaves * 64 * m;
-      if (e < total) {
-        const int part = SPLIT ? (e >= per_part) : 0;
-        const int e2 = e - part * per_part;
-        const int row = e2 / cpr, c = e2 - row * cpr;
+    if constexpr (KPC != 0 && KPC % kFpp == 0) {
+      // every pass full (8 chunks per staged row): one wave instruction
+      // fills 8 staged rows, 1 KB of LDS, straight from global memory
+      // (gfx950 global-to-LDS loads, no register round trip); lane l fills
+      // slot l % 8 of row 8 b + l / 8 with the chunk the swizzle puts there
+      const int lrow = l >> 3, slot = l & 7;
+      for (int b = q; b < kStripOpRows / 8; b += kStripWaves) {
+        const int row = 8 * b + lrow;
+        const int cl = slot ^ ((row >> 1) & 7);
+        const int part = SPLIT ? (cl >> 2) : 0;
+        const int c = SPLIT ? (cl & 3) : cl;
         const int64_t g = row < kStripRows ? r0 + row : c0 + (row - kStripRows);
         const uint16_t *src = (SPLIT && part) ? a.Xlo : a.Xb;
-        v[m] = *reinterpret_cast<const u4 *>(src + g * KP + k0 + 8 * c);
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void *)(src + g * KP + k0 + 8 * c),
+            (__attribute__((address_space(3))) void *)(ops + b * 1024), 16, 0, 0);
       }
-    }
+      __builtin_amdgcn_s_waitcnt(0);  // the wave's staged rows have landed
+    } else {
+      const int cpr = nf >> 3;  // chunks per row and part
+      const int per_part = kStripOpRows * cpr;
+      const int total = per_part * (SPLIT ? 2 : 1);
+      u4 v[kMaxLoads];
 #pragma unroll
-    for (int m = 0; m < kMaxLoads; ++m) {
-      const int e = t + kStripWaves * 64 * m;
-      if (e < total) {
-        const int part = SPLIT ? (e >= per_part) : 0;
-        const int e2 = e - part * per_part;
-        const int row = e2 / cpr, c = e2 - row * cpr;
-        *reinterpret_cast<u4 *>(ops + strip_chunk(row, c + 4 * part)) = v[m];
+      for (int m = 0; m < kMaxLoads; ++m) {
+        const int e = t + kStripWaves * 64 * m;
+        if (e < total) {
+          const int part = SPLIT ? (e >= per_part) : 0;
+          const int e2 = e - part * per_part;
+          const int row = e2 / cpr, c = e2 - row * cpr;
+          const int64_t g = row < kStripRows ? r0 + row : c0 + (row - kStripRows);
+          const uint16_t *src = (SPLIT && part) ? a.Xlo : a.Xb;
+          v[m] = *reinterpret_cast<const u4 *>(src + g * KP + k0 + 8 * c);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kMaxLoads; ++m) {
+        const int e = t + kStripWaves * 64 * m;
+        if (e < total) {
+          const int part = SPLIT ? (e >= per_part) : 0;
+          const int e2 = e - part * per_part;
+          const int row = e2 / cpr, c = e2 - row * cpr;
+          *reinterpret_cast<u4 *>(ops + strip_chunk(row, c + 4 * part)) = v[m];
+        }
       }
     }
     __syncthreads();
