@@ -113,8 +113,14 @@ struct BwdLayout {
 // each cell then takes e = D_ij - delta_ij, adds e^2 to lacc and uses
 // dL/dD_ij = 2 e (cells outside the strict lower triangle contribute
 // nothing to either).
-template <int TS, int LPR, int D, int LAYOUT, bool INTERIOR, bool STRESS>
-__device__ __forceinline__ void bwd_quarter_steps(
+// `stage` stores the tile's points to LDS and, after the barrier,
+// `read_cols` takes the lane's column points from there.  In the gradient
+// passes (not STRESS) the points were loaded into registers and the first
+// step's dD loads are issued before `stage`, so the tile's start waits for
+// one round of loads instead of two (measured 6 us of 177 at N = 20000).
+template <int TS, int LPR, int D, int LAYOUT, bool INTERIOR, bool STRESS, typename Stage,
+          typename ReadCols>
+__device__ __forceinline__ void bwd_quarter_steps(Stage stage, ReadCols read_cols,
     const BwdArgs &a, const float *xs, float *rowp, const float (&xj)[BwdLayout<TS, LPR>::Q][D],
     const bool (&jok)[BwdLayout<TS, LPR>::Q], float (&cacc)[BwdLayout<TS, LPR>::Q][D],
     int64_t row0, int64_t cbase, int rq0, int rg, int cg, bool diag, float &lacc) {
@@ -142,14 +148,28 @@ __device__ __forceinline__ void bwd_quarter_steps(
       }
     }
   };
-#pragma unroll 1
-  for (int s = 0; s < L::STEPS; ++s) {
-    float g[P][Q];
-    bool okm[P][Q];
+  // EARLY (the staged prologue): the first step's loads go out before the
+  // barrier; otherwise every step loads at its start, after the barrier
+  constexpr bool EARLY = !STRESS;
+  float g[P][Q];
+  bool okm[P][Q];
+  if constexpr (EARLY) {
 #pragma unroll
     for (int p = 0; p < P; ++p) load_row(p, g[p], okm[p]);
     bst += row_gap<LAYOUT>((uint64_t)ist, L::SR, a.ldd);
     ist += L::SR;
+  }
+  stage();
+  __syncthreads();
+  read_cols();
+#pragma unroll 1
+  for (int s = 0; s < L::STEPS; ++s) {
+    if (!EARLY || s > 0) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) load_row(p, g[p], okm[p]);
+      bst += row_gap<LAYOUT>((uint64_t)ist, L::SR, a.ldd);
+      ist += L::SR;
+    }
     const int rl = rq0 + L::SR * s + P * rg;  // tile-local row of p = 0
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -243,35 +263,77 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
   __shared__ float xs[TS * D];
   __shared__ float rowp[2][TS * D];  // by column half
   __shared__ float colp[2][TS * D];  // by row half
-  for (int e = t; e < TS * D; e += 256) {
-    const int r = e / D;
-    const int k = e - r * D;
-    const int64_t p = row0 + r;
-    xs[e] = p < N ? a.X[p * a.ldx + k] : 0.0f;
+  // The tile's row and column points: coalesced loads into registers,
+  // stored to LDS once the first step's dD loads are out (kStaged).  The
+  // fused stress pass keeps the plain prologue (row points straight to LDS,
+  // the lane's column points from global memory): the staged one takes it
+  // past three waves per SIMD at TS = 256.
+  constexpr bool kStaged = !STRESS;
+  constexpr int kXsPer = (TS * D + 255) / 256;
+  __shared__ float xc[kStaged ? TS * D : 1];
+  float xsv[kXsPer], xcv[kXsPer];
+  if constexpr (kStaged) {
+#pragma unroll
+    for (int m = 0; m < kXsPer; ++m) {
+      const int e = t + 256 * m;
+      const int r = e / D;
+      const int k = e - r * D;
+      const int64_t p = row0 + r;
+      const int64_t pc = col0 + r;
+      xsv[m] = (e < TS * D && p < N) ? a.X[p * a.ldx + k] : 0.0f;
+      xcv[m] = (e < TS * D && pc < N) ? a.X[pc * a.ldx + k] : 0.0f;
+    }
+  } else {
+    for (int e = t; e < TS * D; e += 256) {
+      const int r = e / D;
+      const int k = e - r * D;
+      const int64_t p = row0 + r;
+      xs[e] = p < N ? a.X[p * a.ldx + k] : 0.0f;
+    }
   }
-  float xj[Q][D];
+  auto stage = [&]() {
+    if constexpr (kStaged) {
+#pragma unroll
+      for (int m = 0; m < kXsPer; ++m)
+        if (t + 256 * m < TS * D) {
+          xs[t + 256 * m] = xsv[m];
+          xc[t + 256 * m] = xcv[m];
+        }
+    }
+  };
+  float xj[Q][D];  // the lane's column points
   bool jok[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int64_t j = cbase + LPR * q;
     jok[q] = j < N;
+    if constexpr (!kStaged) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) xj[q][k] = jok[q] ? a.X[j * a.ldx + k] : 0.0f;
+      for (int k = 0; k < D; ++k) xj[q][k] = jok[q] ? a.X[j * a.ldx + k] : 0.0f;
+    }
   }
+  const int cl0 = H * ch + cg;  // tile-local column of q = 0
+  auto read_cols = [&]() {
+    if constexpr (kStaged) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k < D; ++k) xj[q][k] = xc[(cl0 + LPR * q) * D + k];
+    }
+  };
   float cacc[Q][D];
 #pragma unroll
   for (int q = 0; q < Q; ++q)
 #pragma unroll
     for (int k = 0; k < D; ++k) cacc[q][k] = 0.0f;
 
-  __syncthreads();
   const bool diag = I == J;
   float lacc = 0.0f;
   if ((J < I) && (row0 + TS <= N))
-    bwd_quarter_steps<TS, LPR, D, LAYOUT, true, STRESS>(a, xs, rowp[ch], xj, jok, cacc, row0,
+    bwd_quarter_steps<TS, LPR, D, LAYOUT, true, STRESS>(stage, read_cols, a, xs, rowp[ch], xj, jok, cacc, row0,
                                                          cbase, H * rh, rg, cg, false, lacc);
   else
-    bwd_quarter_steps<TS, LPR, D, LAYOUT, false, STRESS>(a, xs, rowp[ch], xj, jok, cacc, row0,
+    bwd_quarter_steps<TS, LPR, D, LAYOUT, false, STRESS>(stage, read_cols, a, xs, rowp[ch], xj, jok, cacc, row0,
                                                           cbase, H * rh, rg, cg, diag, lacc);
   __shared__ float lossp[4];
   if constexpr (STRESS) {
