@@ -113,11 +113,12 @@ struct BwdLayout {
 // each cell then takes e = D_ij - delta_ij, adds e^2 to lacc and uses
 // dL/dD_ij = 2 e (cells outside the strict lower triangle contribute
 // nothing to either).
-// `stage` stores the tile's points to LDS and, after the barrier,
-// `read_cols` takes the lane's column points from there.  In the gradient
-// passes (not STRESS) the points were loaded into registers and the first
-// step's dD loads are issued before `stage`, so the tile's start waits for
-// one round of loads instead of two (measured 6 us of 177 at N = 20000).
+// `stage` stores the tile's points (loaded into registers with coalesced
+// loads) to LDS and, after the barrier, `read_cols` takes the lane's column
+// points from there.  In the gradient passes (not STRESS) the first step's
+// dD loads are issued before `stage`, so a tile's start waits for one round
+// of loads instead of two; the fused pass, short of registers at TS = 256,
+// loads each step after the barrier.
 template <int TS, int LPR, int D, int LAYOUT, bool INTERIOR, bool STRESS, typename Stage,
           typename ReadCols>
 __device__ __forceinline__ void bwd_quarter_steps(Stage stage, ReadCols read_cols,
@@ -148,9 +149,7 @@ __device__ __forceinline__ void bwd_quarter_steps(Stage stage, ReadCols read_col
       }
     }
   };
-  // EARLY (the staged prologue): the first step's loads go out before the
-  // barrier; otherwise every step loads at its start, after the barrier
-  constexpr bool EARLY = !STRESS;
+  constexpr bool EARLY = !STRESS;  // the first step's loads before the barrier
   float g[P][Q];
   bool okm[P][Q];
   if constexpr (EARLY) {
@@ -264,62 +263,39 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
   __shared__ float rowp[2][TS * D];  // by column half
   __shared__ float colp[2][TS * D];  // by row half
   // The tile's row and column points: coalesced loads into registers,
-  // stored to LDS once the first step's dD loads are out (kStaged).  The
-  // fused stress pass keeps the plain prologue (row points straight to LDS,
-  // the lane's column points from global memory): the staged one takes it
-  // past three waves per SIMD at TS = 256.
-  constexpr bool kStaged = !STRESS;
+  // stored to LDS by `stage` (in the gradient passes after the first step's
+  // dD loads are out), the lane's column points then read from LDS.
   constexpr int kXsPer = (TS * D + 255) / 256;
-  __shared__ float xc[kStaged ? TS * D : 1];
+  __shared__ float xc[TS * D];
   float xsv[kXsPer], xcv[kXsPer];
-  if constexpr (kStaged) {
 #pragma unroll
-    for (int m = 0; m < kXsPer; ++m) {
-      const int e = t + 256 * m;
-      const int r = e / D;
-      const int k = e - r * D;
-      const int64_t p = row0 + r;
-      const int64_t pc = col0 + r;
-      xsv[m] = (e < TS * D && p < N) ? a.X[p * a.ldx + k] : 0.0f;
-      xcv[m] = (e < TS * D && pc < N) ? a.X[pc * a.ldx + k] : 0.0f;
-    }
-  } else {
-    for (int e = t; e < TS * D; e += 256) {
-      const int r = e / D;
-      const int k = e - r * D;
-      const int64_t p = row0 + r;
-      xs[e] = p < N ? a.X[p * a.ldx + k] : 0.0f;
-    }
+  for (int m = 0; m < kXsPer; ++m) {
+    const int e = t + 256 * m;
+    const int r = e / D;
+    const int k = e - r * D;
+    const int64_t p = row0 + r;
+    const int64_t pc = col0 + r;
+    xsv[m] = (e < TS * D && p < N) ? a.X[p * a.ldx + k] : 0.0f;
+    xcv[m] = (e < TS * D && pc < N) ? a.X[pc * a.ldx + k] : 0.0f;
   }
   auto stage = [&]() {
-    if constexpr (kStaged) {
 #pragma unroll
-      for (int m = 0; m < kXsPer; ++m)
-        if (t + 256 * m < TS * D) {
-          xs[t + 256 * m] = xsv[m];
-          xc[t + 256 * m] = xcv[m];
-        }
-    }
+    for (int m = 0; m < kXsPer; ++m)
+      if (t + 256 * m < TS * D) {
+        xs[t + 256 * m] = xsv[m];
+        xc[t + 256 * m] = xcv[m];
+      }
   };
   float xj[Q][D];  // the lane's column points
   bool jok[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int64_t j = cbase + LPR * q;
-    jok[q] = j < N;
-    if constexpr (!kStaged) {
-#pragma unroll
-      for (int k = 0; k < D; ++k) xj[q][k] = jok[q] ? a.X[j * a.ldx + k] : 0.0f;
-    }
-  }
+  for (int q = 0; q < Q; ++q) jok[q] = cbase + LPR * q < N;
   const int cl0 = H * ch + cg;  // tile-local column of q = 0
   auto read_cols = [&]() {
-    if constexpr (kStaged) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q)
+    for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int k = 0; k < D; ++k) xj[q][k] = xc[(cl0 + LPR * q) * D + k];
-    }
+      for (int k = 0; k < D; ++k) xj[q][k] = xc[(cl0 + LPR * q) * D + k];
   };
   float cacc[Q][D];
 #pragma unroll
