@@ -259,14 +259,14 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
   const int64_t col0 = (int64_t)J * TS;
   const int64_t cbase = col0 + H * ch + cg;  // column of q = 0
 
-  __shared__ float xs[TS * D];
+  __shared__ float xs[TS * D];        // the tile's row points
+  __shared__ float xc[TS * D];        // the tile's column points
   __shared__ float rowp[2][TS * D];  // by column half
   __shared__ float colp[2][TS * D];  // by row half
   // The tile's row and column points: coalesced loads into registers,
   // stored to LDS by `stage` (in the gradient passes after the first step's
   // dD loads are out), the lane's column points then read from LDS.
   constexpr int kXsPer = (TS * D + 255) / 256;
-  __shared__ float xc[TS * D];
   float xsv[kXsPer], xcv[kXsPer];
 #pragma unroll
   for (int m = 0; m < kXsPer; ++m) {
