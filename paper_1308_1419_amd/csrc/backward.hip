@@ -244,7 +244,10 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
   using L = BwdLayout<TS, LPR>;
   constexpr int H = L::H;
   constexpr int Q = L::Q;
-  const uint32_t lam = lam0 + xcd_contiguous(blockIdx.x, gridDim.x);
+  // plain block order: the hardware deals consecutive tiles to the eight
+  // XCDs in turn, which reads faster here than one contiguous range of
+  // tiles per XCD (168 against 173 us at N = 20000, TS = 256)
+  const uint32_t lam = lam0 + blockIdx.x;
   uint32_t I, J;
   g_lambda(lam, I, J);
   const int t = threadIdx.x;
