@@ -53,6 +53,8 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+constexpr uint32_t kBwdChunk = 4;  // consecutive tiles per XCD turn
+
 // Lanes per row group in the tiles (16 measured faster than 8: 8 halves the
 // reduction moves per cell but needed three waves per SIMD's worth of
 // registers at TS = 128).
@@ -244,10 +246,17 @@ __global__ __launch_bounds__(256) void edm_bwd_tile(BwdArgs a, uint32_t lam0) {
   using L = BwdLayout<TS, LPR>;
   constexpr int H = L::H;
   constexpr int Q = L::Q;
-  // plain block order: the hardware deals consecutive tiles to the eight
-  // XCDs in turn, which reads faster here than one contiguous range of
-  // tiles per XCD (168 against 173 us at N = 20000, TS = 256)
-  const uint32_t lam = lam0 + blockIdx.x;
+  // Tile order for reads: the hardware deals work-groups to the eight XCDs
+  // in turn; chunks of kBwdChunk consecutive tiles per XCD, dealt in turn,
+  // read faster than one contiguous range of tiles per XCD (which the
+  // write-bound kernels use) or than plain order (at N = 20000, TS = 256:
+  // 168, 173 and 171 us).  The ragged end keeps plain order.
+  uint32_t lam;
+  {
+    const uint32_t b = blockIdx.x, full = gridDim.x / (8u * kBwdChunk) * (8u * kBwdChunk);
+    const uint32_t r = b >> 3;
+    lam = lam0 + (b < full ? ((r / kBwdChunk) * 8u + (b & 7u)) * kBwdChunk + r % kBwdChunk : b);
+  }
   uint32_t I, J;
   g_lambda(lam, I, J);
   const int t = threadIdx.x;
